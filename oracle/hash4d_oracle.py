@@ -1,0 +1,356 @@
+"""FP64 CPU oracle of the DASH 4D hash deformation path.
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product path may import, call or execute
+this module: only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline``
+leg of ``bench.py`` use it.  It shares no code, tables or constants with the HIP
+library; the two meet only through host arrays produced by the seeded input
+generators in ``paper_2507_19141_amd/synth.py``.
+
+What it computes (DASH, arXiv 2507.19141):
+
+* Section 4.2, Eq. 7  -- per-dimension level resolutions (geometric progression).
+* Section 4.2         -- floor/ceil hypervoxel corners of x = (P, t) at each level.
+* Section 4.2, Eq. 8  -- XOR-of-products spatial hash modulo the level table size.
+* Section 4.2, Eq. 9  -- quadrilinear interpolation, levels concatenated into
+                         f_h in R^{L F}, followed by the decoder MLP.
+* Section 4.2, multi-head deformation decoder and Eq. 10 -- heads for position,
+                         rotation and scale, added to the Gaussian attributes.
+* Section 4.3, Eq. 11 -- feature-space smoothness term between x and x + eps.
+* Training (Eq. 12)   -- the gradients of all of the above with respect to the
+                         tables and the decoder weights.
+
+Everything floating-point is FP64, except the one step where the GPU's
+rounding decides an integer: the scaling x * N_l is done in FP32 (round to
+nearest even, no fused multiply-add), so that floor() and therefore the corner
+indices are bit-identical to the kernel's.
+
+Readings of points the paper leaves open (each also listed in the design doc):
+
+ R1  Eq. 7 prints no level exponent; read as N_l = floor(N_min * b**l), the
+     progression of the hash encoding it builds on.  FP64 evaluation is snapped
+     by a 1e-9 relative guard before the floor, and N_{L-1} is pinned to N_max.
+ R2  Space and time each have their own (N_min, N_max); the workload with
+     "growth x2" is read as N_l = min(N_min * 2**l, N_max).
+ R3  Scaling is the literal x * N_l (no half-cell shift).  Lower corner
+     i = min(floor(x N_l), N_l - 1); the ceil corner is i + 1 (same output: at
+     integer positions its weight is exactly zero).  x is clamped to [0, 1]
+     (NaN -> 0), so each dimension has N_l + 1 vertices.
+ R4  Primes: (1, 2654435761, 805459861, 3266489917) for (x, y, z, t); products
+     and XOR wrap at 32 bits, then mod T.
+ R5  A level whose (N_s+1)^3 (N_t+1) vertices fit in T entries is indexed
+     densely (x fastest, then y, z, t), collision-free, with a table of exactly
+     that many rows; every other level is hashed into T rows.
+ R6  Decoder: trunk in -> 64 (ReLU) -> 64 (ReLU); the three heads are single
+     linear layers 64 -> 3 / 4 / 3, stored fused as one 10-row layer.
+     Flat parameter order: W1[64,in], b1[64], W2[64,64], b2[64], W3[10,64], b3[10]
+     (weights row-major, [out, in]).
+ R7  Smoothness: L_r = lam / n * sum_i ||G(x_i) - G(clamp(x_i + eps_i))||^2,
+     x + eps rounded in FP32, gradient through both terms.
+
+Parity pins live in tests/test_oracle_*.py; "parity unpinned" marks what no pin
+covers (the prime set itself: any fixed set of large primes is a correct reading).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+PRIMES = (1, 2654435761, 805459861, 3266489917)
+MASK32 = 0xFFFFFFFF
+HIDDEN = 64
+HEADS = (3, 4, 3)           # delta position, delta rotation (quaternion), delta scale
+OUT = sum(HEADS)
+
+
+# ----------------------------------------------------------------------------
+# Level schedule -- Section 4.2, Eq. 7
+# ----------------------------------------------------------------------------
+def level_resolutions(n_min: int, n_max: int, L: int) -> list[int]:
+    """Eq. 7 under reading R1: N_l = floor(N_min * b**l), b = exp((ln N_max - ln N_min)/(L-1))."""
+    if L < 1 or n_min < 1 or n_max < n_min:
+        raise ValueError("need L >= 1 and 1 <= n_min <= n_max")
+    if L == 1:
+        return [int(n_min)]
+    b = math.exp((math.log(n_max) - math.log(n_min)) / (L - 1))
+    res = []
+    for l in range(L):
+        v = n_min * b ** l
+        res.append(int(math.floor(v * (1.0 + 1e-9))))
+    res[-1] = int(n_max)
+    return res
+
+
+def doubling_resolutions(n_min: int, n_max: int, L: int) -> list[int]:
+    """Reading R2 of a schedule stated as 'growth x2': double each level, clamp at N_max."""
+    return [int(min(n_min * 2 ** l, n_max)) for l in range(L)]
+
+
+# ----------------------------------------------------------------------------
+# Table layout -- Section 4.2 (per-level tables of T_l rows of F features), R5
+# ----------------------------------------------------------------------------
+@dataclass
+class Grid:
+    L: int
+    F: int
+    res_s: list            # spatial resolution per level
+    res_t: list            # temporal resolution per level
+    T: int                 # hash table rows per hashed level
+    dense: list = field(default_factory=list)
+    sizes: list = field(default_factory=list)
+    offsets: list = field(default_factory=list)   # first row of each level, length L+1
+
+    @property
+    def E(self) -> int:
+        return self.offsets[-1]
+
+
+def make_grid(L, F, res_s, res_t, T) -> Grid:
+    """Per-level row counts and offsets: dense iff (N_s+1)^3 (N_t+1) <= T (R5)."""
+    g = Grid(L=L, F=F, res_s=[int(r) for r in res_s], res_t=[int(r) for r in res_t], T=int(T))
+    off = 0
+    g.offsets.append(0)
+    for l in range(L):
+        nv = (g.res_s[l] + 1) ** 3 * (g.res_t[l] + 1)
+        d = nv <= g.T
+        g.dense.append(d)
+        g.sizes.append(nv if d else g.T)
+        off += g.sizes[-1]
+        g.offsets.append(off)
+    return g
+
+
+# ----------------------------------------------------------------------------
+# Corners, indices and weights -- Section 4.2 (floor/ceil, Eq. 8)
+# ----------------------------------------------------------------------------
+def clamp_unit_f32(x: np.ndarray) -> np.ndarray:
+    """Clamp to [0, 1] in FP32 (R3); NaN maps to 0 as IEEE fmax/fmin do."""
+    x = np.asarray(x, dtype=np.float32)
+    return np.fmin(np.fmax(x, np.float32(0.0)), np.float32(1.0))
+
+
+def cell_position(x32: np.ndarray, N: int):
+    """Lower hypervoxel corner and fractional offset along one dimension (R3).
+
+    pos = fp32(x * N) with FP32 round-to-nearest; i = min(floor(pos), N - 1);
+    frac = pos - i, which is exact in FP32 and is returned as FP64.
+    """
+    pos = (x32.astype(np.float32) * np.float32(N)).astype(np.float32)
+    i = np.minimum(np.floor(pos).astype(np.int64), N - 1)
+    frac = pos.astype(np.float64) - i.astype(np.float64)
+    return i, frac
+
+
+def dense_index(vx, vy, vz, vt, Ns: int) -> np.ndarray:
+    """Collision-free row of vertex (vx, vy, vz, vt) on a dense level (R5), x fastest."""
+    S = Ns + 1
+    return vx + S * (vy + S * (vz + S * vt))
+
+
+def hash_index(vx, vy, vz, vt, T: int) -> np.ndarray:
+    """Eq. 8: (XOR_i v_i * pi_i) mod T, products and XOR wrapped to 32 bits (R4)."""
+    h = np.zeros(np.shape(vx), dtype=np.uint64)
+    for v, p in zip((vx, vy, vz, vt), PRIMES):
+        h ^= (np.asarray(v, dtype=np.uint64) * np.uint64(p)) & np.uint64(MASK32)
+    return (h % np.uint64(T)).astype(np.int64)
+
+
+def corners(xyzt: np.ndarray, grid: Grid):
+    """Rows and weights of the 16 corners at every level.
+
+    Returns (rows [n, L, 16] int64 -- table row including the level offset,
+    weights [n, L, 16] float64).  Corner c takes the upper vertex along
+    dimension d iff bit d of c is set (x = bit 0, y = bit 1, z = bit 2, t = bit 3);
+    its weight is the product over dimensions of frac (upper) or 1 - frac (lower).
+    """
+    x32 = clamp_unit_f32(xyzt)
+    n = x32.shape[0]
+    rows = np.zeros((n, grid.L, 16), dtype=np.int64)
+    wts = np.zeros((n, grid.L, 16), dtype=np.float64)
+    for l in range(grid.L):
+        res = (grid.res_s[l],) * 3 + (grid.res_t[l],)
+        lo, fr = zip(*(cell_position(x32[:, d], res[d]) for d in range(4)))
+        for c in range(16):
+            up = [(c >> d) & 1 for d in range(4)]
+            v = [lo[d] + up[d] for d in range(4)]
+            w = np.ones(n, dtype=np.float64)
+            for d in range(4):
+                w = w * (fr[d] if up[d] else 1.0 - fr[d])
+            if grid.dense[l]:
+                idx = dense_index(v[0], v[1], v[2], v[3], grid.res_s[l])
+            else:
+                idx = hash_index(v[0], v[1], v[2], v[3], grid.T)
+            rows[:, l, c] = grid.offsets[l] + idx
+            wts[:, l, c] = w
+    return rows, wts
+
+
+# ----------------------------------------------------------------------------
+# Encoder G_4D -- Section 4.2, Eq. 9
+# ----------------------------------------------------------------------------
+def encode(xyzt: np.ndarray, table: np.ndarray, grid: Grid) -> np.ndarray:
+    """f_h = G_4D(x) in R^{L F}: per level sum_c w_c * theta[row_c], levels concatenated.
+
+    ``table`` is [E, F]; its values are taken exactly (FP32 or BF16 values up-cast).
+    Output [n, L*F] FP64, feature index l*F + f.
+    """
+    rows, wts = corners(xyzt, grid)
+    th = np.asarray(table, dtype=np.float64)
+    n = rows.shape[0]
+    out = np.zeros((n, grid.L * grid.F), dtype=np.float64)
+    for l in range(grid.L):
+        acc = np.zeros((n, grid.F), dtype=np.float64)
+        for c in range(16):
+            acc += wts[:, l, c:c + 1] * th[rows[:, l, c]]
+        out[:, l * grid.F:(l + 1) * grid.F] = acc
+    return out
+
+
+def encode_backward(xyzt: np.ndarray, d_feat: np.ndarray, grid: Grid, scale: float = 1.0) -> np.ndarray:
+    """Gradient of <f_h, d_feat> with respect to the table: d_theta[row_c] += scale * w_c * d_feat_l.
+
+    f_h is linear in the table, so this is the exact transpose of ``encode``.
+    Returns [E, F] FP64.
+    """
+    rows, wts = corners(xyzt, grid)
+    g = np.asarray(d_feat, dtype=np.float64)
+    out = np.zeros((grid.E, grid.F), dtype=np.float64)
+    for l in range(grid.L):
+        gl = g[:, l * grid.F:(l + 1) * grid.F]
+        for c in range(16):
+            np.add.at(out, rows[:, l, c], scale * wts[:, l, c:c + 1] * gl)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Multi-head deformation decoder -- Section 4.2 (Eq. 9 trunk, heads, Eq. 10)
+# ----------------------------------------------------------------------------
+def param_count(n_in: int, hidden: int = HIDDEN, out: int = OUT) -> int:
+    return hidden * n_in + hidden + hidden * hidden + hidden + out * hidden + out
+
+
+def unpack_params(flat: np.ndarray, n_in: int, hidden: int = HIDDEN, out: int = OUT):
+    """Split the flat parameter vector in the order of R6 into FP64 arrays."""
+    p = np.asarray(flat, dtype=np.float64)
+    if p.size != param_count(n_in, hidden, out):
+        raise ValueError("parameter vector has the wrong length")
+    shapes = [("W1", (hidden, n_in)), ("b1", (hidden,)), ("W2", (hidden, hidden)),
+              ("b2", (hidden,)), ("W3", (out, hidden)), ("b3", (out,))]
+    d, k = {}, 0
+    for name, shp in shapes:
+        m = int(np.prod(shp))
+        d[name] = p[k:k + m].reshape(shp)
+        k += m
+    return d
+
+
+def pack_params(d: dict) -> np.ndarray:
+    return np.concatenate([d[k].reshape(-1) for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def mlp_forward(flat_params: np.ndarray, f_h: np.ndarray):
+    """phi_d then the heads: h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2), delta = W3 h2 + b3.
+
+    Returns (delta [n, 10], cache) in FP64; delta = [dx(3) | dr(4) | ds(3)].
+    """
+    f = np.asarray(f_h, dtype=np.float64)
+    P = unpack_params(flat_params, f.shape[1])
+    z1 = f @ P["W1"].T + P["b1"]
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ P["W2"].T + P["b2"]
+    h2 = np.maximum(z2, 0.0)
+    delta = h2 @ P["W3"].T + P["b3"]
+    return delta, {"f": f, "z1": z1, "h1": h1, "z2": z2, "h2": h2, "P": P}
+
+
+def mlp_backward(flat_params: np.ndarray, f_h: np.ndarray, d_delta: np.ndarray, scale: float = 1.0):
+    """Chain rule through the decoder.  ReLU passes gradient where its input is > 0.
+
+    Returns (d_feat [n, in], d_params flat) in FP64, both multiplied by ``scale``.
+    """
+    _, c = mlp_forward(flat_params, f_h)
+    P = c["P"]
+    g3 = np.asarray(d_delta, dtype=np.float64) * scale
+    dW3 = g3.T @ c["h2"]
+    db3 = g3.sum(axis=0)
+    g2 = (g3 @ P["W3"]) * (c["z2"] > 0)
+    dW2 = g2.T @ c["h1"]
+    db2 = g2.sum(axis=0)
+    g1 = (g2 @ P["W2"]) * (c["z1"] > 0)
+    dW1 = g1.T @ c["f"]
+    db1 = g1.sum(axis=0)
+    d_feat = g1 @ P["W1"]
+    d_params = pack_params({"W1": dW1, "b1": db1, "W2": dW2, "b2": db2, "W3": dW3, "b3": db3})
+    return d_feat, d_params
+
+
+def deform(x, r, s, delta):
+    """Eq. 10: (x', r', s') = (x + dx, r + dr, s + ds); rotation delta added raw."""
+    delta = np.asarray(delta, dtype=np.float64)
+    return (np.asarray(x, np.float64) + delta[:, 0:3],
+            np.asarray(r, np.float64) + delta[:, 3:7],
+            np.asarray(s, np.float64) + delta[:, 7:10])
+
+
+# ----------------------------------------------------------------------------
+# Full deformation step (forward and backward)
+# ----------------------------------------------------------------------------
+def deform_forward(xyzt, table, grid: Grid, flat_params):
+    """x -> f_h (Eq. 9) -> decoder -> delta.  Returns (f_h, delta)."""
+    f = encode(xyzt, table, grid)
+    delta, _ = mlp_forward(flat_params, f)
+    return f, delta
+
+
+def deform_backward(xyzt, table, grid: Grid, flat_params, d_delta, scale: float = 1.0):
+    """Gradients of <delta, d_delta>: (d_table [E,F], d_params flat, d_feat [n, L F])."""
+    f = encode(xyzt, table, grid)
+    d_feat, d_params = mlp_backward(flat_params, f, d_delta, scale)
+    d_table = encode_backward(xyzt, d_feat, grid, 1.0)
+    return d_table, d_params, d_feat
+
+
+# ----------------------------------------------------------------------------
+# Smoothness regulariser -- Section 4.3, Eq. 11
+# ----------------------------------------------------------------------------
+def perturbed(xyzt, eps) -> np.ndarray:
+    """x + eps rounded in FP32, then clamped to the unit hypercube (R3, R7)."""
+    s = (np.asarray(xyzt, np.float32) + np.asarray(eps, np.float32)).astype(np.float32)
+    return clamp_unit_f32(s)
+
+
+def smoothness(xyzt, eps, table, grid: Grid, lam: float = 1.0):
+    """L_r = lam/n * sum_i ||G(x_i) - G(x_i + eps_i)||^2 and its table gradient (R7)."""
+    n = np.asarray(xyzt).shape[0]
+    if n == 0:
+        return 0.0, np.zeros((grid.E, grid.F))
+    xp = perturbed(xyzt, eps)
+    d = encode(xyzt, table, grid) - encode(xp, table, grid)
+    loss = lam / n * float(np.sum(d * d))
+    g = (2.0 * lam / n) * d
+    d_table = encode_backward(xyzt, g, grid) - encode_backward(xp, g, grid)
+    return loss, d_table
+
+
+# ----------------------------------------------------------------------------
+# Precision form helpers (BF16 storage of FP32 masters)
+# ----------------------------------------------------------------------------
+def bf16_bits(x32: np.ndarray) -> np.ndarray:
+    """Round FP32 to BF16 with round-to-nearest-even; returns the uint16 bit patterns.
+
+    NaN stays a quiet NaN.  Plain definition: add 0x7FFF plus the lowest kept bit
+    to the FP32 bit pattern and drop the low 16 bits.
+    """
+    u = np.asarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) & np.uint64(0xFFFF)
+    nan = np.isnan(np.asarray(x32, dtype=np.float32))
+    r = np.where(nan, (u >> np.uint64(16)) | np.uint64(0x40), r)
+    return r.astype(np.uint16)
+
+
+def bf16_value(bits: np.ndarray) -> np.ndarray:
+    """BF16 bit patterns to their exact FP64 values."""
+    u = np.asarray(bits, dtype=np.uint16).astype(np.uint32) << np.uint32(16)
+    return u.view(np.float32).astype(np.float64)

@@ -1,0 +1,322 @@
+"""Pins of the CPU oracle's encoder against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: exact integer
+arithmetic, exhaustive enumeration, a library routine (scipy's regular-grid
+linear interpolation, which in 4D is quadrilinear interpolation), closed forms
+and brute force on tiny grids.  Section 4.2 of DASH (Eqs. 7-9) defines what is
+pinned.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.interpolate import RegularGridInterpolator
+
+from oracle import hash4d_oracle as O
+from paper_2507_19141_amd import synth
+
+
+# ---------------------------------------------------------------- Eq. 7 ----
+def exact_level_res(n_min, n_max, L, l):
+    """Largest integer n with n <= n_min * (n_max/n_min)**(l/(L-1)), in exact integers:
+    n**(L-1) * n_min**l <= n_min**(L-1) * n_max**l."""
+    if L == 1:
+        return n_min
+    k = L - 1
+    rhs = n_min ** k * n_max ** l
+    lo, hi = 1, n_max + 1
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if mid ** k * n_min ** l <= rhs:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+@pytest.mark.parametrize("n_min,n_max,L", [(16, 2048, 16), (16, 150, 16), (4, 32, 4), (4, 16, 4),
+                                           (2, 4096, 12), (3, 1000, 7), (8, 8, 5), (5, 77, 2)])
+def test_schedule_matches_exact_integer_floor(n_min, n_max, L):
+    got = O.level_resolutions(n_min, n_max, L)
+    want = [exact_level_res(n_min, n_max, L, l) for l in range(L)]
+    assert got == want
+    assert got[0] == n_min and got[-1] == n_max
+    assert all(a <= b for a, b in zip(got, got[1:]))
+
+
+def test_schedule_random_configs():
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        n_min = int(rng.integers(1, 64))
+        n_max = int(rng.integers(n_min, 5000))
+        L = int(rng.integers(1, 33))
+        assert O.level_resolutions(n_min, n_max, L) == [exact_level_res(n_min, n_max, L, l) for l in range(L)]
+
+
+def test_schedule_fp_guard_case():
+    # 4 * b**3 with b = exp(ln(4)/3) is 15.999999999999996 in FP64; the exact value is 16.
+    assert O.level_resolutions(4, 16, 4) == [4, 6, 10, 16]
+    assert O.doubling_resolutions(4, 16, 4) == [4, 8, 16, 16]
+    assert O.doubling_resolutions(4, 32, 4) == [4, 8, 16, 32]
+
+
+def test_paper_scene_layout():
+    # Worked by hand: (16+1)^4 = 83521 and (22+1)^3 (18+1) = 231173 fit in 2^19, the next level does not.
+    rs = O.level_resolutions(16, 2048, 16)
+    rt = O.level_resolutions(16, 150, 16)
+    g = O.make_grid(16, 2, rs, rt, 1 << 19)
+    assert g.dense == [True, True] + [False] * 14
+    assert g.sizes[:2] == [17 ** 4, 23 ** 3 * 19]
+    assert g.E == 17 ** 4 + 23 ** 3 * 19 + 14 * (1 << 19)
+
+
+# ------------------------------------------------------- dense indexing ----
+@pytest.mark.parametrize("Ns,Nt", [(1, 1), (2, 3), (4, 4), (3, 7)])
+def test_dense_index_is_bijection(Ns, Nt):
+    S = Ns + 1
+    v = np.array(np.meshgrid(np.arange(S), np.arange(S), np.arange(S), np.arange(Nt + 1), indexing="ij"))
+    v = v.reshape(4, -1)
+    idx = O.dense_index(v[0], v[1], v[2], v[3], Ns)
+    assert idx.min() == 0 and idx.max() == S ** 3 * (Nt + 1) - 1
+    assert np.unique(idx).size == idx.size
+    # x is the fastest-moving coordinate
+    assert O.dense_index(1, 0, 0, 0, Ns) == 1 and O.dense_index(0, 1, 0, 0, Ns) == S
+    assert O.dense_index(0, 0, 0, 1, Ns) == S ** 3
+
+
+# ---------------------------------------------------------------- Eq. 8 ----
+def bigint_hash(v, T):
+    h = 0
+    for vi, p in zip(v, (1, 2654435761, 805459861, 3266489917)):
+        h ^= (int(vi) * p) % (1 << 32)
+    return h % T
+
+
+@pytest.mark.parametrize("T", [1 << 12, 1 << 19, 3 ** 9, 1000003, 1])
+def test_hash_against_python_bigints(T):
+    rng = np.random.default_rng(1)
+    v = rng.integers(0, 1 << 24, size=(4, 500))
+    v[:, :4] = [[0, 1, 2 ** 24, 12345]] * 4
+    got = O.hash_index(v[0], v[1], v[2], v[3], T)
+    want = [bigint_hash(v[:, k], T) for k in range(v.shape[1])]
+    assert got.tolist() == want
+
+
+def test_hash_x_neighbours_share_a_pair():
+    # pi_1 = 1: for even v_x, vertex v_x + 1 lands on the neighbouring row (bit 0 flips).
+    rng = np.random.default_rng(2)
+    v = rng.integers(0, 1 << 20, size=(4, 300))
+    v[0] &= ~1
+    a = O.hash_index(v[0], v[1], v[2], v[3], 1 << 16)
+    b = O.hash_index(v[0] + 1, v[1], v[2], v[3], 1 << 16)
+    assert np.all(a ^ b == 1)
+
+
+def test_primes_are_large_primes_except_unit_x():
+    def is_prime(p):
+        return p > 1 and all(p % d for d in range(2, int(math.isqrt(p)) + 1))
+    assert O.PRIMES[0] == 1
+    assert all(is_prime(p) and p > 2 ** 28 for p in O.PRIMES[1:])
+    assert len(set(O.PRIMES)) == 4
+
+
+# ---------------------------------------------------- corners & weights ----
+def small_grid(T=1 << 12):
+    return O.make_grid(4, 2, O.doubling_resolutions(4, 32, 4), O.doubling_resolutions(4, 16, 4), T)
+
+
+def test_partition_of_unity_and_constant_table():
+    _, x = synth.small_inputs(0, 1000)
+    g = small_grid()
+    _, w = O.corners(x, g)
+    assert np.allclose(w.sum(axis=2), 1.0, atol=1e-15, rtol=0)
+    assert (w >= 0).all()
+    f = O.encode(x, np.full((g.E, 2), 0.375), g)
+    assert np.allclose(f, 0.375, atol=1e-15, rtol=0)
+
+
+def test_corner_count_and_distinct_vertices():
+    _, x = synth.small_inputs(3, 500)
+    g = small_grid()
+    r, _ = O.corners(x, g)
+    # dense level: the 16 corners are 16 distinct rows inside the level's block
+    assert all(len(set(row)) == 16 for row in r[:, 0, :].tolist())
+    for l in range(4):
+        assert r[:, l].min() >= g.offsets[l] and r[:, l].max() < g.offsets[l + 1]
+
+
+def test_vertex_recovery_exact():
+    # x on a vertex of every level (x = k/4 and N_l in {4, 8, 16, 32}): f_h = theta at that vertex.
+    g = small_grid(T=1 << 12)
+    rng = np.random.default_rng(4)
+    table = rng.standard_normal((g.E, 2))
+    k = rng.integers(0, 5, size=(300, 4))
+    x = (k / 4.0).astype(np.float32)
+    f = O.encode(x, table, g)
+    for l in range(4):
+        v = [k[:, d] * (g.res_s[l] if d < 3 else g.res_t[l]) // 4 for d in range(4)]
+        if g.dense[l]:
+            idx = O.dense_index(*v, g.res_s[l])
+        else:
+            idx = np.array([bigint_hash([v[d][i] for d in range(4)], g.T) for i in range(300)])
+        assert np.array_equal(f[:, 2 * l:2 * l + 2], table[g.offsets[l] + idx])
+
+
+def test_upper_boundary_is_last_vertex():
+    g = small_grid()
+    table = np.arange(g.E * 2, dtype=np.float64).reshape(g.E, 2)
+    f = O.encode(np.ones((1, 4), np.float32), table, g)
+    assert f[0, 0] == table[O.dense_index(4, 4, 4, 4, 4), 0]
+
+
+def test_clamp_and_nan():
+    g = small_grid()
+    rng = np.random.default_rng(5)
+    table = rng.standard_normal((g.E, 2))
+    x = np.array([[-0.5, 1.5, np.nan, 0.25], [0.0, 1.0, 0.0, 0.25]], np.float32)
+    f = O.encode(x, table, g)
+    assert np.array_equal(f[0], f[1])
+
+
+def test_affine_reproduction_on_dense_level():
+    # Multilinear interpolation reproduces affine data exactly: theta(v) = a.v + b  =>  f = a.(x N) + b.
+    Ns, Nt = 5, 3
+    g = O.make_grid(1, 2, [Ns], [Nt], 10 ** 6)
+    assert g.dense == [True]
+    S = Ns + 1
+    v = np.array(np.meshgrid(np.arange(S), np.arange(S), np.arange(S), np.arange(Nt + 1), indexing="ij")).reshape(4, -1)
+    a = np.array([[0.3, -1.1], [2.0, 0.5], [-0.7, 0.25], [1.5, -3.0]])
+    b = np.array([0.125, -2.0])
+    table = np.zeros((g.E, 2))
+    table[O.dense_index(*v, Ns)] = v.T @ a + b
+    _, x = synth.small_inputs(6, 400)
+    f = O.encode(x, table, g)
+    pos = np.stack([(x[:, d] * np.float32(Ns if d < 3 else Nt)).astype(np.float32) for d in range(4)], 1)
+    assert np.allclose(f, pos.astype(np.float64) @ a + b, atol=1e-12, rtol=0)
+
+
+def test_dense_level_matches_scipy_regular_grid_interpolation():
+    # Library pin: 4D linear interpolation on the regular vertex grid.
+    Ns, Nt = 6, 4
+    g = O.make_grid(1, 2, [Ns], [Nt], 10 ** 6)
+    S = Ns + 1
+    rng = np.random.default_rng(8)
+    table = rng.standard_normal((g.E, 2))
+    vals = np.zeros((S, S, S, Nt + 1, 2))
+    for vx in range(S):
+        for vy in range(S):
+            for vz in range(S):
+                for vt in range(Nt + 1):
+                    vals[vx, vy, vz, vt] = table[O.dense_index(vx, vy, vz, vt, Ns)]
+    axes = [np.arange(S)] * 3 + [np.arange(Nt + 1)]
+    rgi = RegularGridInterpolator(axes, vals, method="linear")
+    _, x = synth.small_inputs(9, 500)
+    x[:3] = [[1, 1, 1, 1], [0, 0, 0, 0], [1, 0, 0.5, 1]]
+    pos = np.stack([(x[:, d] * np.float32(Ns if d < 3 else Nt)).astype(np.float32) for d in range(4)], 1)
+    assert np.allclose(O.encode(x, table, g), rgi(pos.astype(np.float64)), atol=1e-12, rtol=0)
+
+
+def test_t_zero_reduces_to_trilinear():
+    # All t = 0: only t-lower corners weigh; result = trilinear interpolation of the t = 0 slab.
+    Ns, Nt = 5, 3
+    g = O.make_grid(1, 1, [Ns], [Nt], 10 ** 6)
+    S = Ns + 1
+    rng = np.random.default_rng(10)
+    table = rng.standard_normal((g.E, 1))
+    slab = np.zeros((S, S, S))
+    for vx in range(S):
+        for vy in range(S):
+            for vz in range(S):
+                slab[vx, vy, vz] = table[O.dense_index(vx, vy, vz, 0, Ns), 0]
+    rgi = RegularGridInterpolator([np.arange(S)] * 3, slab, method="linear")
+    _, x = synth.small_inputs(11, 300)
+    x[:, 3] = 0
+    pos = (x[:, :3] * np.float32(Ns)).astype(np.float32).astype(np.float64)
+    assert np.allclose(O.encode(x, table, g)[:, 0], rgi(pos), atol=1e-12, rtol=0)
+
+
+def lerp(a, b, t):
+    return a + (b - a) * t
+
+
+def test_brute_force_unit_grid_dense_T16():
+    # L = 1, N = 1 in every dimension, T = 16: the level is dense and row c is corner c, so
+    # f(x) is the 16-term multilinear polynomial, written here as nested linear interpolation.
+    g = O.make_grid(1, 1, [1], [1], 16)
+    assert g.dense == [True] and g.E == 16
+    rng = np.random.default_rng(12)
+    th = rng.standard_normal(16)
+    x = rng.random((200, 4)).astype(np.float32)
+    X = x.astype(np.float64)
+
+    def f(p):
+        vt = []
+        for ct in range(2):
+            vz = []
+            for cz in range(2):
+                vy = []
+                for cy in range(2):
+                    vy.append(lerp(th[0 + 2 * cy + 4 * cz + 8 * ct], th[1 + 2 * cy + 4 * cz + 8 * ct], p[0]))
+                vz.append(lerp(vy[0], vy[1], p[1]))
+            vt.append(lerp(vz[0], vz[1], p[2]))
+        return lerp(vt[0], vt[1], p[3])
+    want = np.array([f(X[i]) for i in range(200)])
+    assert np.allclose(O.encode(x, th[:, None], g)[:, 0], want, atol=1e-13, rtol=0)
+
+
+def test_brute_force_tiny_hashed_grid_against_dict():
+    # T = 8 < 16 vertices: hashed.  Reference: dict vertex -> row (Python bigints), exact rationals.
+    T = 8
+    g = O.make_grid(1, 1, [1], [2], T)
+    assert g.dense == [False]
+    rng = np.random.default_rng(13)
+    th = rng.integers(-50, 50, size=T)
+    rows = {(a, b, c, d): bigint_hash((a, b, c, d), T)
+            for a in range(2) for b in range(2) for c in range(2) for d in range(3)}
+    x = (rng.integers(0, 64, size=(100, 4)) / 64.0).astype(np.float32)
+    got = O.encode(x, th[:, None].astype(np.float64), g)[:, 0]
+    for i in range(100):
+        fr = [Fraction(float(x[i, d])) * (1 if d < 3 else 2) for d in range(4)]
+        lo = [min(int(v), (1 if d < 3 else 2) - 1) for d, v in enumerate(fr)]
+        acc = Fraction(0)
+        for c in range(16):
+            up = [(c >> d) & 1 for d in range(4)]
+            w = Fraction(1)
+            for d in range(4):
+                fd = fr[d] - lo[d]
+                w *= fd if up[d] else 1 - fd
+            acc += w * int(th[rows[tuple(lo[d] + up[d] for d in range(4))]])
+        assert got[i] == float(acc)
+
+
+# ----------------------------------------------------- backward = transpose ----
+def test_backward_is_exact_transpose():
+    _, x = synth.small_inputs(14, 700)
+    g = small_grid()
+    rng = np.random.default_rng(15)
+    th = rng.standard_normal((g.E, 2))
+    gf = rng.standard_normal((700, 8))
+    lhs = np.sum(O.encode(x, th, g) * gf)
+    rhs = np.sum(th * O.encode_backward(x, gf, g))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
+    # scale multiplies through
+    assert np.allclose(O.encode_backward(x, gf, g, 0.25), 0.25 * O.encode_backward(x, gf, g), rtol=0, atol=1e-15)
+
+
+def test_backward_matches_central_differences():
+    # f_h is linear in the table, so central differences are exact up to rounding.
+    _, x = synth.small_inputs(16, 64)
+    g = small_grid()
+    rng = np.random.default_rng(17)
+    th = rng.standard_normal((g.E, 2))
+    gf = rng.standard_normal((64, 8))
+    grad = O.encode_backward(x, gf, g)
+    rows, _ = O.corners(x, g)
+    touched = np.unique(rows)
+    for r in rng.choice(touched, 20, replace=False):
+        for f in range(2):
+            e = np.zeros_like(th)
+            e[r, f] = 1e-3
+            fd = (np.sum(O.encode(x, th + e, g) * gf) - np.sum(O.encode(x, th - e, g) * gf)) / 2e-3
+            assert abs(fd - grad[r, f]) <= 1e-9 * (1 + abs(fd))

@@ -1,0 +1,138 @@
+"""Planted mistakes: each test breaks the CPU oracle in one plausible way and checks
+that at least one pin notices.  The mistakes are planted in the oracle, on the CPU,
+through monkeypatching; the oracle's own file is never changed."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import hash4d_oracle as O
+from tests import test_oracle_decoder as D
+from tests import test_oracle_encoder as E
+
+
+def expect_pin_failure(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_schedule_without_level_exponent_is_caught(monkeypatch):
+    def garbled(n_min, n_max, L):   # Eq. 7 as printed, b not raised to l
+        b = math.exp((math.log(n_max) - math.log(n_min)) / (L - 1))
+        return [n_min] + [int(n_min * b)] * (L - 2) + [n_max]
+    monkeypatch.setattr(O, "level_resolutions", garbled)
+    expect_pin_failure(E.test_schedule_matches_exact_integer_floor, 16, 2048, 16)
+
+
+def test_schedule_without_fp_guard_is_caught(monkeypatch):
+    def unguarded(n_min, n_max, L):
+        b = math.exp((math.log(n_max) - math.log(n_min)) / (L - 1))
+        return [int(math.floor(n_min * b ** l)) for l in range(L)]
+    monkeypatch.setattr(O, "level_resolutions", unguarded)
+    expect_pin_failure(E.test_schedule_fp_guard_case)
+
+
+def test_swapped_weights_are_caught(monkeypatch):
+    real = O.cell_position
+
+    def swapped(x32, N):
+        i, fr = real(x32, N)
+        return i, 1.0 - fr
+    monkeypatch.setattr(O, "cell_position", swapped)
+    expect_pin_failure(E.test_affine_reproduction_on_dense_level)
+    expect_pin_failure(E.test_dense_level_matches_scipy_regular_grid_interpolation)
+
+
+def test_fp64_scaling_is_caught(monkeypatch):
+    def fp64_scale(x32, N):
+        pos = x32.astype(np.float64) * N
+        i = np.minimum(np.floor(pos).astype(np.int64), N - 1)
+        return i, pos - i
+    monkeypatch.setattr(O, "cell_position", fp64_scale)
+    expect_pin_failure(E.test_affine_reproduction_on_dense_level)
+
+
+def test_transposed_dense_order_is_caught(monkeypatch):
+    def z_fastest(vx, vy, vz, vt, Ns):
+        S = Ns + 1
+        return vz + S * (vy + S * (vx + S * vt))
+    monkeypatch.setattr(O, "dense_index", z_fastest)
+    expect_pin_failure(E.test_dense_index_is_bijection, 2, 3)
+
+
+def test_corner_bits_out_of_step_with_weights_is_caught(monkeypatch):
+    def mixed(xyzt, grid):
+        x32 = O.clamp_unit_f32(xyzt)
+        n = x32.shape[0]
+        rows = np.zeros((n, grid.L, 16), dtype=np.int64)
+        wts = np.zeros((n, grid.L, 16))
+        for l in range(grid.L):
+            res = (grid.res_s[l],) * 3 + (grid.res_t[l],)
+            lo, fr = zip(*(O.cell_position(x32[:, d], res[d]) for d in range(4)))
+            for c in range(16):
+                up = [(c >> d) & 1 for d in range(4)]
+                v = [lo[d] + up[d] for d in range(4)]
+                w = np.ones(n)
+                for d in range(4):
+                    w = w * (fr[d] if up[3 - d] else 1.0 - fr[d])
+                idx = O.dense_index(*v, grid.res_s[l]) if grid.dense[l] else O.hash_index(*v, grid.T)
+                rows[:, l, c] = grid.offsets[l] + idx
+                wts[:, l, c] = w
+        return rows, wts
+    monkeypatch.setattr(O, "corners", mixed)
+    expect_pin_failure(E.test_dense_level_matches_scipy_regular_grid_interpolation)
+    expect_pin_failure(E.test_brute_force_unit_grid_dense_T16)
+
+
+def test_hash_without_32bit_wrap_is_caught(monkeypatch):
+    def no_wrap(vx, vy, vz, vt, T):
+        h = np.zeros(np.shape(vx), dtype=np.uint64)
+        for v, p in zip((vx, vy, vz, vt), O.PRIMES):
+            h ^= np.asarray(v, dtype=np.uint64) * np.uint64(p)
+        return (h % np.uint64(T)).astype(np.int64)
+    monkeypatch.setattr(O, "hash_index", no_wrap)
+    expect_pin_failure(E.test_hash_against_python_bigints, 3 ** 9)
+
+
+def test_hash_with_sum_instead_of_xor_is_caught(monkeypatch):
+    def summed(vx, vy, vz, vt, T):
+        h = np.zeros(np.shape(vx), dtype=np.uint64)
+        for v, p in zip((vx, vy, vz, vt), O.PRIMES):
+            h = (h + np.asarray(v, dtype=np.uint64) * np.uint64(p)) & np.uint64(0xFFFFFFFF)
+        return (h % np.uint64(T)).astype(np.int64)
+    monkeypatch.setattr(O, "hash_index", summed)
+    expect_pin_failure(E.test_hash_against_python_bigints, 1 << 12)
+
+
+def test_backward_without_weights_is_caught(monkeypatch):
+    def unweighted(xyzt, d_feat, grid, scale=1.0):
+        rows, _ = O.corners(xyzt, grid)
+        out = np.zeros((grid.E, grid.F))
+        for l in range(grid.L):
+            for c in range(16):
+                np.add.at(out, rows[:, l, c], scale * d_feat[:, l * grid.F:(l + 1) * grid.F] / 16)
+        return out
+    monkeypatch.setattr(O, "encode_backward", unweighted)
+    expect_pin_failure(E.test_backward_is_exact_transpose)
+
+
+def test_dropped_bias_is_caught(monkeypatch):
+    real = O.unpack_params
+
+    def no_b2(flat, n_in, hidden=64, out=10):
+        d = real(flat, n_in, hidden, out)
+        d["b2"] = np.zeros_like(d["b2"])
+        return d
+    monkeypatch.setattr(O, "unpack_params", no_b2)
+    expect_pin_failure(D.test_decoder_forward_and_backward_match_torch, 8)
+
+
+def test_one_sided_smoothness_gradient_is_caught(monkeypatch):
+    def one_sided(xyzt, eps, table, grid, lam=1.0):
+        n = xyzt.shape[0]
+        xp = O.perturbed(xyzt, eps)
+        d = O.encode(xyzt, table, grid) - O.encode(xp, table, grid)
+        return lam / n * float(np.sum(d * d)), O.encode_backward(xyzt, 2 * lam / n * d, grid)
+    monkeypatch.setattr(O, "smoothness", one_sided)
+    # the value check passes, the central differences do not
+    expect_pin_failure(D.test_smoothness_value_and_central_differences)
