@@ -1,0 +1,138 @@
+/*
+ * hash4d.h -- C ABI of libhash4d.so, the MI355X (gfx950) implementation of the
+ * DASH 4D hash deformation path (arXiv 2507.19141, Section 4.2 and Section 4.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers marked (host) are host memory; every other data pointer is device
+ *    memory allocated and owned by the caller.  The library never frees or keeps
+ *    a caller pointer after the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *    enqueued asynchronously on it; arguments are validated synchronously first.
+ *  - Every call returns an h4d_status.  On a negative status nothing has been
+ *    enqueued and h4d_last_error() (thread-local, static storage) says why.
+ *  - n == 0 is valid and enqueues nothing.  n must not exceed 2^31 - 1.
+ *  - Gradient outputs ACCUMULATE (+=) unless stated otherwise, so the caller
+ *    zeroes them first.
+ *  - Positions `xyzt` are FP32 [n, 4] (x, y, z, t), 16-byte aligned.  Values are
+ *    clamped to [0, 1] (NaN counts as 0); normalising scene coordinates into the
+ *    unit cube is the caller's job.
+ *  - No entry point allocates device memory.  Scratch space, where needed, is a
+ *    caller-provided workspace whose size a *_workspace_bytes call reports.
+ */
+#ifndef HASH4D_H
+#define HASH4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define H4D_MAX_LEVELS 32
+#define H4D_HIDDEN 64     /* decoder trunk width */
+#define H4D_MAX_OUT 16    /* decoder output rows, padded */
+
+typedef enum {
+    H4D_OK = 0,
+    H4D_EINVAL = -1,        /* invalid argument (null pointer, bad size, bad grid, misalignment) */
+    H4D_EUNSUPPORTED = -2,  /* valid but not built (e.g. an unsupported width or dtype) */
+    H4D_EHIP = -3,          /* the HIP runtime reported an error; its text is in h4d_last_error() */
+    H4D_ENOPLAN = -4        /* a batched plan handle is null or was destroyed */
+} h4d_status;
+
+typedef enum {
+    H4D_F32 = 0,    /* plain FP32 path */
+    H4D_BF16 = 1,   /* BF16 tables / BF16 MFMA decoder with FP32 accumulation */
+    H4D_F64 = 2     /* FP64 instantiation, meant for finite-difference gradient checks */
+} h4d_dtype;
+
+typedef enum {
+    H4D_SCHEDULE_GEOMETRIC = 0, /* Eq. 7: N_l = floor(N_min b^l), b = (N_max/N_min)^(1/(L-1)) */
+    H4D_SCHEDULE_DOUBLING = 1   /* N_l = min(N_min 2^l, N_max) */
+} h4d_schedule;
+
+/* Multiresolution 4D grid (Section 4.2).  Host struct, filled by h4d_grid_init.
+ * Level l has spatial resolution res_s[l] along x, y, z and temporal resolution
+ * res_t[l] along t, so (res_s+1)^3 (res_t+1) vertices.  A level whose vertices fit
+ * in T rows is stored densely (collision-free, x fastest, then y, z, t) in exactly
+ * that many rows; every other level is hashed (Eq. 8) into T rows.  The table is
+ * one [E, F] row-major array, E = offset[L]; level l owns rows
+ * [offset[l], offset[l+1]). */
+typedef struct {
+    int32_t L;                          /* levels, 1..32 */
+    int32_t F;                          /* features per row: 1, 2, 4 or 8 */
+    int64_t T;                          /* rows of a hashed level, 1..2^30 */
+    int32_t res_s[H4D_MAX_LEVELS];      /* 1..2^24 */
+    int32_t res_t[H4D_MAX_LEVELS];      /* 1..2^24 */
+    int64_t offset[H4D_MAX_LEVELS + 1]; /* first row of each level; offset[L] = E */
+    uint8_t dense[H4D_MAX_LEVELS];      /* 1 = dense level */
+    uint32_t prime[4];                  /* hash multipliers for x, y, z, t */
+} h4d_grid;
+
+/* Decoder shape (Section 4.2, Eq. 9 and the multi-head decoder).  in = L F,
+ * hidden = 64, out = 10 (dx 3 | drot 4 | dscale 3).  Parameters are one flat
+ * array in the order W1[hidden, in], b1[hidden], W2[hidden, hidden], b2[hidden],
+ * W3[out, hidden], b3[out], weights row-major [out, in]. */
+typedef struct {
+    int32_t in;       /* 4..128, multiple of 4 (multiple of 8 for BF16) */
+    int32_t hidden;   /* must be 64 */
+    int32_t out;      /* 1..16 */
+} h4d_mlp;
+
+/* Text of the last error on this thread ("" if none).  Never NULL. */
+const char* h4d_last_error(void);
+
+/* Library version string. */
+const char* h4d_version(void);
+
+/* ---------------------------------------------------------------- grid ---- */
+
+/* Level resolutions of one dimension (Section 4.2, Eq. 7).  Geometric: the
+ * progression of Eq. 7 with its level exponent, evaluated in FP64 with a 1e-9
+ * relative guard before the floor, last level pinned to n_max.  Doubling:
+ * min(n_min 2^l, n_max).  res_out (host) receives L values.
+ * EINVAL: L not in 1..32, n_min < 1, n_max < n_min, n_max > 2^24, res_out NULL. */
+h4d_status h4d_grid_schedule(int32_t L, int32_t n_min, int32_t n_max, int32_t rule, int32_t* res_out);
+
+/* Fill *g (host) from explicit per-level resolutions (host arrays of L values):
+ * dense flags, offsets and the default primes (1, 2654435761, 805459861,
+ * 3266489917).  EINVAL on any out-of-range field or if E F >= 2^31. */
+h4d_status h4d_grid_init(h4d_grid* g, int32_t L, int32_t F, const int32_t* res_s, const int32_t* res_t, int64_t T);
+
+/* Rows E of the table described by *g (host), or -1 if *g is invalid. */
+int64_t h4d_grid_rows(const h4d_grid* g);
+
+/* ------------------------------------------------------------- encoder ---- */
+
+/* Forward encoder G_4D (Section 4.2, Eqs. 8-9).  For each query and level: scale
+ * x by the level resolution in FP32 (round to nearest, no fused multiply-add),
+ * take the 16 corners of the hypervoxel, index them (dense or hashed), gather F
+ * features per corner and interpolate quadrilinearly.
+ *   table   [E, F] of table_dt (F32, BF16 bit patterns, or F64)
+ *   feat    [n, L F], feature l F + f; FP32 for F32/BF16 tables, FP64 for F64.
+ * Written, not accumulated.  Deterministic (no atomics). */
+h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* table,
+                         const float* xyzt, int64_t n, void* feat, void* stream);
+
+/* Backward of hash4d_encode with respect to the table (the exact transpose of the
+ * interpolation in Eq. 9): d_table[row_c, f] += grad_scale * w_c * d_feat[q, l F + f]
+ * over every query, level and corner.  Corners and weights are recomputed from
+ * xyzt.  grad_dt F32: d_feat and d_table are FP32; F64: both FP64.
+ *   d_feat  [n, L F]     d_table [E, F] (+=)
+ * Uses device atomics: the summation order, hence the last bits, vary run to run. */
+h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
+                                  const void* d_feat, float grad_scale, void* d_table, void* stream);
+
+/* Test hook: the table row (level offset included) and FP32 weight of the 16
+ * corners of every query and level.  Corner c is upper along x, y, z, t iff bit
+ * 0, 1, 2, 3 of c is set.
+ *   rows [n, L, 16] int32      w [n, L, 16] FP32 (either may be NULL) */
+h4d_status hash4d_corner_indices(const h4d_grid* g, const float* xyzt, int64_t n,
+                                 int32_t* rows, float* w, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HASH4D_H */

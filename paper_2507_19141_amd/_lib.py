@@ -1,0 +1,164 @@
+"""ctypes binding of libhash4d.so (declared in include/hash4d.h).
+
+Argument marshalling only: every function here forwards to the C entry point of
+the same name, passing raw device pointers (``tensor.data_ptr()``) and the
+current HIP stream.  Nothing is computed in Python, and there is no fallback:
+if the library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhash4d.so")
+
+MAX_LEVELS = 32
+F32, BF16, F64 = 0, 1, 2
+SCHEDULE_GEOMETRIC, SCHEDULE_DOUBLING = 0, 1
+STATUS = {0: "H4D_OK", -1: "H4D_EINVAL", -2: "H4D_EUNSUPPORTED", -3: "H4D_EHIP", -4: "H4D_ENOPLAN"}
+
+
+class H4DError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} -> {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    """Mirror of h4d_grid."""
+    _fields_ = [("L", ctypes.c_int32), ("F", ctypes.c_int32), ("T", ctypes.c_int64),
+                ("res_s", ctypes.c_int32 * MAX_LEVELS), ("res_t", ctypes.c_int32 * MAX_LEVELS),
+                ("offset", ctypes.c_int64 * (MAX_LEVELS + 1)), ("dense", ctypes.c_uint8 * MAX_LEVELS),
+                ("prime", ctypes.c_uint32 * 4)]
+
+    @property
+    def E(self) -> int:
+        return int(self.offset[self.L])
+
+    def dense_list(self) -> list:
+        return [bool(self.dense[l]) for l in range(self.L)]
+
+    def offsets(self) -> list:
+        return [int(self.offset[l]) for l in range(self.L + 1)]
+
+
+class Mlp(ctypes.Structure):
+    """Mirror of h4d_mlp."""
+    _fields_ = [("in_", ctypes.c_int32), ("hidden", ctypes.c_int32), ("out", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_I32, _I64, _F32, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
+_GP = ctypes.POINTER(Grid)
+_MP = ctypes.POINTER(Mlp)
+
+# name -> (restype, argtypes); the order follows include/hash4d.h
+SIGNATURES = {
+    "h4d_last_error": (ctypes.c_char_p, []),
+    "h4d_version": (ctypes.c_char_p, []),
+    "h4d_grid_schedule": (_I32, [_I32, _I32, _I32, _I32, ctypes.POINTER(_I32)]),
+    "h4d_grid_init": (_I32, [_GP, _I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _I64]),
+    "h4d_grid_rows": (_I64, [_GP]),
+    "hash4d_encode": (_I32, [_GP, _I32, _P, _P, _I64, _P, _P]),
+    "hash4d_encode_backward": (_I32, [_GP, _I32, _P, _I64, _P, _F32, _P, _P]),
+    "hash4d_corner_indices": (_I32, [_GP, _P, _I64, _P, _P, _P]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the library once.  torch is imported first so that the library binds to
+    the HIP runtime torch already loaded (one runtime per process)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:
+        import torch  # noqa: F401  (binds libamdhip64.so.7 before the library does)
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2507_19141_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().h4d_last_error().decode()
+
+
+def _check(fn: str, st: int) -> None:
+    if st != 0:
+        raise H4DError(fn, st, last_error())
+
+
+def ptr(x) -> int | None:
+    """Device (or host) address of a tensor, an int address, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def stream_handle(stream=None) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------------ grid ----
+def h4d_grid_schedule(L: int, n_min: int, n_max: int, rule: int = SCHEDULE_GEOMETRIC) -> list:
+    out = (_I32 * L)()
+    _check("h4d_grid_schedule", load().h4d_grid_schedule(L, n_min, n_max, rule, out))
+    return list(out)
+
+
+def h4d_grid_init(L: int, F: int, res_s, res_t, T: int) -> Grid:
+    g = Grid()
+    rs = (_I32 * L)(*[int(v) for v in res_s])
+    rt = (_I32 * L)(*[int(v) for v in res_t])
+    _check("h4d_grid_init", load().h4d_grid_init(ctypes.byref(g), L, F, rs, rt, T))
+    return g
+
+
+def h4d_grid_rows(g: Grid) -> int:
+    return int(load().h4d_grid_rows(ctypes.byref(g)))
+
+
+# --------------------------------------------------------------- encoder ----
+def hash4d_encode(g: Grid, table_dt: int, table, xyzt, n: int, feat, stream=None) -> None:
+    _check("hash4d_encode", load().hash4d_encode(ctypes.byref(g), table_dt, ptr(table), ptr(xyzt), n, ptr(feat),
+                                                 stream_handle(stream)))
+
+
+def hash4d_encode_backward(g: Grid, grad_dt: int, xyzt, n: int, d_feat, grad_scale: float, d_table,
+                           stream=None) -> None:
+    _check("hash4d_encode_backward",
+           load().hash4d_encode_backward(ctypes.byref(g), grad_dt, ptr(xyzt), n, ptr(d_feat), grad_scale,
+                                         ptr(d_table), stream_handle(stream)))
+
+
+def hash4d_corner_indices(g: Grid, xyzt, n: int, rows, w, stream=None) -> None:
+    _check("hash4d_corner_indices", load().hash4d_corner_indices(ctypes.byref(g), ptr(xyzt), n, ptr(rows), ptr(w),
+                                                                 stream_handle(stream)))
+
+
+def hip_runtimes_loaded() -> list:
+    """Distinct libamdhip64 files mapped into this process (should be exactly one)."""
+    seen = set()
+    with open("/proc/self/maps") as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) >= 6 and "libamdhip64" in parts[-1]:
+                seen.add(os.path.realpath(parts[-1]))
+    return sorted(seen)

@@ -1,0 +1,167 @@
+// Device helpers of the 4D hash encoder: hypervoxel corners, rows, weights and
+// table-row loads (DASH Section 4.2, Eqs. 8-9).  Included by the kernel sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "h4d_internal.h"
+
+namespace h4d {
+
+// Clamp to [0, 1]; NaN fails both comparisons and becomes 0.
+__device__ __forceinline__ float clamp_unit(float x) {
+    x = (x >= 0.0f) ? x : 0.0f;
+    return (x <= 1.0f) ? x : 1.0f;
+}
+
+// Lower vertex and fractional offset along one dimension: pos = x * N rounded once
+// in FP32 (__fmul_rn keeps it out of any fused multiply-add), i = min(floor(pos),
+// N - 1), frac = pos - i, which is exact in FP32.
+__device__ __forceinline__ void cell_1d(float x, int N, int& i, float& fr) {
+    const float pos = __fmul_rn(x, (float)N);
+    i = min((int)floorf(pos), N - 1);
+    fr = pos - (float)i;
+}
+
+// Per (query, level) state: the lower vertex and fractional offsets.
+struct Cell {
+    int ix, iy, iz, it;
+    float fx, fy, fz, ft;
+};
+
+__device__ __forceinline__ Cell level_cell(const DevGrid& g, int l, float4 x) {
+    Cell c;
+    const int Ns = g.res_s[l], Nt = g.res_t[l];
+    cell_1d(clamp_unit(x.x), Ns, c.ix, c.fx);
+    cell_1d(clamp_unit(x.y), Ns, c.iy, c.fy);
+    cell_1d(clamp_unit(x.z), Ns, c.iz, c.fz);
+    cell_1d(clamp_unit(x.w), Nt, c.it, c.ft);
+    return c;
+}
+
+// Table rows of the 16 corners; corner k is upper along x, y, z, t iff bit 0, 1, 2, 3
+// of k is set.  Dense levels: x fastest, then y, z, t.  Hashed levels: XOR of the
+// 32-bit wrapped products with the primes (Eq. 8), then mod T.
+__device__ __forceinline__ void level_rows(const DevGrid& g, int l, const Cell& c, uint32_t row[16]) {
+    const uint32_t off = g.off[l];
+    if ((g.dense_bits >> l) & 1u) {
+        const uint32_t S = (uint32_t)g.res_s[l] + 1u;
+        const uint32_t S2 = S * S, S3 = S2 * S;
+        const uint32_t base = off + (uint32_t)c.ix + S * ((uint32_t)c.iy + S * ((uint32_t)c.iz + S * (uint32_t)c.it));
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            row[k] = base + (k & 1) + ((k >> 1) & 1) * S + ((k >> 2) & 1) * S2 + ((k >> 3) & 1) * S3;
+    } else {
+        const uint32_t hx0 = (uint32_t)c.ix * g.prime[0], hx1 = hx0 + g.prime[0];
+        const uint32_t hy0 = (uint32_t)c.iy * g.prime[1], hy1 = hy0 + g.prime[1];
+        const uint32_t hz0 = (uint32_t)c.iz * g.prime[2], hz1 = hz0 + g.prime[2];
+        const uint32_t ht0 = (uint32_t)c.it * g.prime[3], ht1 = ht0 + g.prime[3];
+        if (g.tmask) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t h = ((k & 1) ? hx1 : hx0) ^ ((k & 2) ? hy1 : hy0) ^ ((k & 4) ? hz1 : hz0) ^
+                                   ((k & 8) ? ht1 : ht0);
+                row[k] = off + (h & g.tmask);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t h = ((k & 1) ? hx1 : hx0) ^ ((k & 2) ? hy1 : hy0) ^ ((k & 4) ? hz1 : hz0) ^
+                                   ((k & 8) ? ht1 : ht0);
+                row[k] = off + (h % g.T);
+            }
+        }
+    }
+}
+
+// Quadrilinear weights of the 16 corners in precision W.
+template <typename W>
+__device__ __forceinline__ void level_weights(const Cell& c, W w[16]) {
+    const W wx[2] = {W(1) - W(c.fx), W(c.fx)};
+    const W wy[2] = {W(1) - W(c.fy), W(c.fy)};
+    const W wz[2] = {W(1) - W(c.fz), W(c.fz)};
+    const W wt[2] = {W(1) - W(c.ft), W(c.ft)};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) w[k] = ((wx[k & 1] * wy[(k >> 1) & 1]) * wz[(k >> 2) & 1]) * wt[k >> 3];
+}
+
+// ---- table element types ----
+struct bf16_t {
+    uint16_t bits;
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+
+// Round-to-nearest-even FP32 -> BF16 bit pattern (NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Load the F features of one row as type A.
+template <typename TT, int F, typename A>
+struct RowLoad;
+
+template <int F, typename A>
+struct RowLoad<float, F, A> {
+    __device__ __forceinline__ static void load(const float* __restrict__ t, uint32_t row, A (&v)[F]) {
+        const float* p = t + (size_t)row * F;
+        if constexpr (F == 1) {
+            v[0] = (A)p[0];
+        } else if constexpr (F == 2) {
+            const float2 a = *reinterpret_cast<const float2*>(p);
+            v[0] = (A)a.x; v[1] = (A)a.y;
+        } else {
+#pragma unroll
+            for (int j = 0; j < F; j += 4) {
+                const float4 a = *reinterpret_cast<const float4*>(p + j);
+                v[j] = (A)a.x; v[j + 1] = (A)a.y; v[j + 2] = (A)a.z; v[j + 3] = (A)a.w;
+            }
+        }
+    }
+};
+
+template <int F, typename A>
+struct RowLoad<bf16_t, F, A> {
+    __device__ __forceinline__ static void load(const bf16_t* __restrict__ t, uint32_t row, A (&v)[F]) {
+        const uint16_t* p = reinterpret_cast<const uint16_t*>(t) + (size_t)row * F;
+        if constexpr (F == 1) {
+            v[0] = (A)bf16_to_f32(p[0]);
+        } else if constexpr (F == 2) {
+            const uint32_t a = *reinterpret_cast<const uint32_t*>(p);
+            v[0] = (A)__uint_as_float(a << 16); v[1] = (A)__uint_as_float(a & 0xffff0000u);
+        } else if constexpr (F == 4) {
+            const uint2 a = *reinterpret_cast<const uint2*>(p);
+            v[0] = (A)__uint_as_float(a.x << 16); v[1] = (A)__uint_as_float(a.x & 0xffff0000u);
+            v[2] = (A)__uint_as_float(a.y << 16); v[3] = (A)__uint_as_float(a.y & 0xffff0000u);
+        } else {
+            const uint4 a = *reinterpret_cast<const uint4*>(p);
+            const uint32_t u[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v[2 * j] = (A)__uint_as_float(u[j] << 16);
+                v[2 * j + 1] = (A)__uint_as_float(u[j] & 0xffff0000u);
+            }
+        }
+    }
+};
+
+template <int F, typename A>
+struct RowLoad<double, F, A> {
+    __device__ __forceinline__ static void load(const double* __restrict__ t, uint32_t row, A (&v)[F]) {
+        const double* p = t + (size_t)row * F;
+#pragma unroll
+        for (int j = 0; j < F; ++j) v[j] = (A)p[j];
+    }
+};
+
+// Compute type of each table type: FP32 for F32/BF16 tables, FP64 for FP64 tables.
+template <typename TT> struct AccOf { using type = float; };
+template <> struct AccOf<double> { using type = double; };
+
+__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+}  // namespace h4d

@@ -1,0 +1,124 @@
+"""The C ABI library loads, exports every symbol include/hash4d.h declares, and its
+host-only logic (level schedule, table layout, argument validation) agrees with
+the oracle.  No call here launches GPU work."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import hash4d_oracle as O
+from paper_2507_19141_amd import _lib, synth
+from tests.util import assert_same_layout, lib_grid, oracle_grid
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hash4d.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s+\*?([a-z0-9_]+)\s*\(",
+                                 text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = declared_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in hash4d.h but not exported"
+    # every declared function has a binding of the same name, and vice versa
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_version_and_empty_error():
+    assert b"gfx950" in _lib.load().h4d_version()
+    _lib.h4d_grid_schedule(4, 4, 16)
+    assert _lib.last_error() == ""
+
+
+@pytest.mark.parametrize("rule", [_lib.SCHEDULE_GEOMETRIC, _lib.SCHEDULE_DOUBLING])
+def test_schedule_matches_oracle(rule):
+    rng = np.random.default_rng(30)
+    for _ in range(300):
+        n_min = int(rng.integers(1, 100))
+        n_max = int(rng.integers(n_min, 1 << 14))
+        L = int(rng.integers(1, 33))
+        want = (O.level_resolutions if rule == _lib.SCHEDULE_GEOMETRIC else O.doubling_resolutions)(n_min, n_max, L)
+        assert _lib.h4d_grid_schedule(L, n_min, n_max, rule) == want
+
+
+@pytest.mark.parametrize("w", [synth.ENCODER_SMALL, synth.PAPER_SCENE], ids=lambda w: w.name)
+def test_layout_matches_oracle(w):
+    og, lg = oracle_grid(w), lib_grid(w)
+    assert_same_layout(og, lg)
+    assert _lib.h4d_grid_rows(lg) == og.E
+    assert list(lg.prime) == list(O.PRIMES)
+
+
+def test_layout_random_grids():
+    rng = np.random.default_rng(31)
+    for _ in range(200):
+        L = int(rng.integers(1, 33))
+        F = int(rng.choice([1, 2, 4, 8]))
+        T = int(rng.integers(1, 1 << 20))
+        rs = rng.integers(1, 300, size=L).tolist()
+        rt = rng.integers(1, 300, size=L).tolist()
+        og = O.make_grid(L, F, rs, rt, T)
+        if og.E * F >= 1 << 31:
+            continue
+        assert_same_layout(og, _lib.h4d_grid_init(L, F, rs, rt, T))
+
+
+@pytest.mark.parametrize("args,frag", [
+    ((0, 2, [4], [4], 64), "L=0"),
+    ((33, 2, [4] * 33, [4] * 33, 64), "L=33"),
+    ((2, 3, [4, 4], [4, 4], 64), "F=3"),
+    ((2, 2, [0, 4], [4, 4], 64), "resolution"),
+    ((2, 2, [4, 4], [4, 1 << 25], 64), "resolution"),
+    ((2, 2, [4, 4], [4, 4], 0), "T=0"),
+    ((2, 2, [4, 4], [4, 4], (1 << 30) + 1), "T="),
+    ((3, 8, [1 << 20] * 3, [1 << 20] * 3, 1 << 30), "exceeds 2^31"),
+])
+def test_grid_init_rejects(args, frag):
+    L = args[0]
+    g = _lib.Grid()
+    rs = (_lib.ctypes.c_int32 * max(L, 1))(*args[2][:max(L, 1)])
+    rt = (_lib.ctypes.c_int32 * max(L, 1))(*args[3][:max(L, 1)])
+    st = _lib.load().h4d_grid_init(_lib.ctypes.byref(g), L, args[1], rs, rt, args[4])
+    assert st == -1
+    assert frag in _lib.last_error()
+
+
+def test_schedule_rejects():
+    for args in [(0, 4, 16, 0), (4, 0, 16, 0), (4, 16, 4, 0), (4, 4, 1 << 25, 0), (4, 4, 16, 7)]:
+        with pytest.raises(_lib.H4DError) as e:
+            _lib.h4d_grid_schedule(*args)
+        assert e.value.status == -1
+
+
+def test_corrupted_grid_is_rejected_before_launch():
+    g = lib_grid(synth.ENCODER_SMALL)
+    g.offset[2] += 1
+    assert _lib.h4d_grid_rows(g) == -1
+    fake = 1 << 20   # never dereferenced: validation fails first
+    st = _lib.load().hash4d_encode(_lib.ctypes.byref(g), 0, fake, fake, 10, fake, None)
+    assert st == -1 and "inconsistent" in _lib.last_error()
+
+
+def test_entry_points_validate_without_launching():
+    lib = _lib.load()
+    g = lib_grid(synth.ENCODER_SMALL)
+    gp = _lib.ctypes.byref(g)
+    fake = 1 << 20
+    assert lib.hash4d_encode(gp, 0, fake, fake, 0, fake, None) == 0                 # n = 0: no-op
+    assert lib.hash4d_encode(gp, 0, None, fake, 5, fake, None) == -1                # NULL table
+    assert lib.hash4d_encode(gp, 0, fake, fake + 4, 5, fake, None) == -1            # misaligned xyzt
+    assert "aligned" in _lib.last_error()
+    assert lib.hash4d_encode(gp, 7, fake, fake, 5, fake, None) == -1                # unknown dtype
+    assert lib.hash4d_encode(gp, 0, fake, fake, -1, fake, None) == -1               # negative n
+    assert lib.hash4d_encode(gp, 0, fake, fake, 1 << 31, fake, None) == -1          # n too large
+    assert lib.hash4d_encode_backward(gp, 1, fake, 5, fake, 1.0, fake, None) == -1  # grads must be F32/F64
+    assert lib.hash4d_corner_indices(gp, fake, 5, None, None, None) == -1
+    assert lib.hash4d_encode(None, 0, fake, fake, 5, fake, None) == -1

@@ -1,0 +1,219 @@
+"""GPU parity of the 4D hash encoder (Section 4.2, Eqs. 8-9) through the C ABI.
+
+Corner rows are compared bit-exactly; FP32 features within 1e-5 and FP32 table
+gradients within 1e-4 of the FP64 oracle (relative to the oracle's magnitude
+scale); the FP64 instantiation within 1e-12.
+"""
+import numpy as np
+import pytest
+
+from oracle import hash4d_oracle as O
+from paper_2507_19141_amd import _lib, synth
+from tests.util import (RTOL_F32, RTOL_GRAD, assert_same_layout, lib_grid, needs_gpu, oracle_grid,
+                        scaled_close)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    needs_gpu()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def empty(shape, dtype):
+    import torch
+    return torch.full(shape, float("nan") if dtype.is_floating_point else -1, dtype=dtype, device="cuda")
+
+
+def edge_points(og):
+    """Vertices, boundaries, values just below vertex boundaries, out-of-range and NaN."""
+    pts = [[0, 0, 0, 0], [1, 1, 1, 1], [1, 0, 1, 0], [-0.25, 1.75, 0.5, 2.0], [np.nan, 0.5, np.nan, 0.25],
+           [np.inf, -np.inf, 0.5, 0.5]]
+    rng = np.random.default_rng(40)
+    for l in range(og.L):
+        for N, d in ((og.res_s[l], rng.integers(0, 3)), (og.res_t[l], 3)):
+            for v in rng.integers(1, N + 1, size=6):
+                p = rng.random(4)
+                p[d] = np.nextafter(np.float32(v / N), np.float32(0))
+                pts.append(p)
+                q = rng.random(4)
+                q[d] = np.float32(v / N)
+                pts.append(q)
+    pts.append([np.nextafter(np.float32(1), np.float32(0))] * 4)
+    return np.asarray(pts, dtype=np.float32)
+
+
+def encoder_case(w, n, seed, edges=True, table_scale=1e-4):
+    og = oracle_grid(w)
+    lg = lib_grid(w)
+    assert_same_layout(og, lg)
+    if w.n > 100_000:
+        rng, x = synth.scene_inputs(n, seed)
+    else:
+        rng, x = synth.small_inputs(seed, n)
+    if edges:
+        x = np.concatenate([x, edge_points(og)])
+    table = synth.table_init(og.E, w.F, rng, table_scale)
+    return og, lg, x, table, rng
+
+
+def run_corners(lg, x):
+    import torch
+    n = x.shape[0]
+    rows = empty((n, lg.L, 16), torch.int32)
+    wts = empty((n, lg.L, 16), torch.float32)
+    _lib.hash4d_corner_indices(lg, dev(x), n, rows, wts)
+    return host(rows), host(wts)
+
+
+def run_encode(lg, dt, table_dev, x):
+    import torch
+    n = x.shape[0]
+    out = empty((n, lg.L * lg.F), torch.float64 if dt == _lib.F64 else torch.float32)
+    _lib.hash4d_encode(lg, dt, table_dev, dev(x), n, out)
+    return host(out)
+
+
+def run_backward(lg, dt, x, gf, E, scale=1.0):
+    import torch
+    n = x.shape[0]
+    tdt = torch.float64 if dt == _lib.F64 else torch.float32
+    d_table = torch.zeros((E, lg.F), dtype=tdt, device="cuda")
+    _lib.hash4d_encode_backward(lg, dt, dev(x), n, dev(gf.astype(np.float64 if dt == _lib.F64 else np.float32)),
+                                scale, d_table)
+    return host(d_table)
+
+
+# ------------------------------------------------------------------ corners ----
+@pytest.mark.parametrize("w", [synth.ENCODER_SMALL, synth.PAPER_SCENE], ids=lambda w: w.name)
+def test_corner_rows_bit_exact(w):
+    og, lg, x, _, _ = encoder_case(w, 4096, 0)
+    rows, wts = run_corners(lg, x)
+    ref_rows, ref_w = O.corners(x, og)
+    assert np.array_equal(rows, ref_rows.astype(np.int32))
+    assert np.abs(wts - ref_w).max() <= 1e-6
+
+
+def test_corner_rows_paper_scene_full_size_sampled():
+    # the configuration the benchmark runs (n = 200k clustered), checked on 4096 sampled queries
+    w = synth.PAPER_SCENE
+    og, lg, x, _, _ = encoder_case(w, w.n, 0, edges=False)
+    rows, _ = run_corners(lg, x)
+    idx = np.random.default_rng(41).choice(w.n, 4096, replace=False)
+    ref_rows, _ = O.corners(x[idx], og)
+    assert np.array_equal(rows[idx], ref_rows.astype(np.int32))
+
+
+# ------------------------------------------------------------------ forward ----
+def test_encode_f32_small():
+    og, lg, x, table, _ = encoder_case(synth.ENCODER_SMALL, 4096, 1)
+    got = run_encode(lg, _lib.F32, dev(table), x)
+    ref = O.encode(x, table, og)
+    scaled_close(got, ref, O.encode(x, np.abs(table), og), RTOL_F32, "f_h")
+
+
+def test_encode_bf16_table_exact_inputs():
+    # BF16 storage: both sides read the same BF16 values; the arithmetic is FP32.
+    import torch
+    og, lg, x, table, _ = encoder_case(synth.ENCODER_SMALL, 4096, 2)
+    bits = O.bf16_bits(table)
+    got = run_encode(lg, _lib.BF16, dev(bits.view(np.int16)), x)
+    tb = O.bf16_value(bits)
+    scaled_close(got, O.encode(x, tb, og), O.encode(x, np.abs(tb), og), RTOL_F32, "f_h bf16")
+    del torch
+
+
+def test_encode_f64_instantiation():
+    og, lg, x, table, _ = encoder_case(synth.ENCODER_SMALL, 2048, 3)
+    t64 = table.astype(np.float64) * 1.2345678901
+    got = run_encode(lg, _lib.F64, dev(t64), x)
+    scaled_close(got, O.encode(x, t64, og), O.encode(x, np.abs(t64), og), 1e-12, "f_h f64")
+
+
+@pytest.mark.parametrize("F,T,n,L", [(1, 3000, 1037, 3), (4, 1 << 12, 777, 4), (8, 1 << 10, 300, 2),
+                                     (2, 1, 65, 1), (2, 4099, 4096 + 255, 5)])
+def test_encode_widths_sizes_and_ragged(F, T, n, L):
+    rs = O.doubling_resolutions(3, 40, L)
+    rt = O.doubling_resolutions(2, 9, L)
+    og = O.make_grid(L, F, rs, rt, T)
+    lg = _lib.h4d_grid_init(L, F, rs, rt, T)
+    assert_same_layout(og, lg)
+    rng, x = synth.small_inputs(4, n)
+    table = synth.table_init(og.E, F, rng, 1.0)
+    got = run_encode(lg, _lib.F32, dev(table), x)
+    scaled_close(got, O.encode(x, table, og), O.encode(x, np.abs(table), og), RTOL_F32, "f_h")
+    rows, _ = run_corners(lg, x)
+    assert np.array_equal(rows, O.corners(x, og)[0].astype(np.int32))
+
+
+def test_encode_paper_scene_full_size_sampled():
+    w = synth.PAPER_SCENE
+    og, lg, x, table, _ = encoder_case(w, w.n, 5, edges=False)
+    got = run_encode(lg, _lib.F32, dev(table), x)
+    idx = np.random.default_rng(42).choice(w.n, 4096, replace=False)
+    xs = x[idx]
+    scaled_close(got[idx], O.encode(xs, table, og), O.encode(xs, np.abs(table), og), RTOL_F32, "f_h 200k")
+
+
+def test_encode_is_deterministic_and_n0_is_noop():
+    import torch
+    og, lg, x, table, _ = encoder_case(synth.ENCODER_SMALL, 4096, 6)
+    td = dev(table)
+    a = run_encode(lg, _lib.F32, td, x)
+    b = run_encode(lg, _lib.F32, td, x)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    out = torch.full((4, 8), 7.0, device="cuda")
+    _lib.hash4d_encode(lg, _lib.F32, td, dev(x[:4]), 0, out)
+    assert (host(out) == 7.0).all()
+
+
+# ----------------------------------------------------------------- backward ----
+def test_encode_backward_f32_small():
+    og, lg, x, _, rng = encoder_case(synth.ENCODER_SMALL, 4096, 7)
+    gf = synth.upstream(x.shape[0], og.L * og.F, rng)
+    got = run_backward(lg, _lib.F32, x, gf, og.E, 0.5)
+    ref = O.encode_backward(x, gf, og, 0.5)
+    scaled_close(got, ref, O.encode_backward(x, np.abs(gf), og, 0.5), RTOL_GRAD, "d_table")
+
+
+def test_encode_backward_f64():
+    og, lg, x, _, rng = encoder_case(synth.ENCODER_SMALL, 2048, 8)
+    gf = synth.upstream(x.shape[0], og.L * og.F, rng).astype(np.float64)
+    got = run_backward(lg, _lib.F64, x, gf, og.E)
+    scaled_close(got, O.encode_backward(x, gf, og), O.encode_backward(x, np.abs(gf), og), 1e-12, "d_table f64")
+
+
+def test_encode_backward_accumulates():
+    import torch
+    og, lg, x, _, rng = encoder_case(synth.ENCODER_SMALL, 1000, 9, edges=False)
+    gf = synth.upstream(1000, og.L * og.F, rng)
+    d = torch.ones((og.E, og.F), dtype=torch.float32, device="cuda")
+    _lib.hash4d_encode_backward(lg, _lib.F32, dev(x), 1000, dev(gf), 1.0, d)
+    ref = 1.0 + O.encode_backward(x, gf, og)
+    scaled_close(host(d), ref, 1.0 + O.encode_backward(x, np.abs(gf), og), RTOL_GRAD, "d_table +=")
+
+
+def test_encode_backward_paper_scene_full_size_property():
+    # At n = 200k: <u, d_table> = <G(u), g> for random u (the backward is the exact
+    # transpose of the forward), with G(u) evaluated by the oracle on every query.
+    w = synth.PAPER_SCENE
+    og, lg, x, _, rng = encoder_case(w, w.n, 10, edges=False)
+    gf = synth.upstream(w.n, og.L * og.F, rng)
+    d_table = run_backward(lg, _lib.F32, x, gf, og.E).astype(np.float64)
+    u = rng.standard_normal((og.E, og.F))
+    lhs = float(np.sum(u * d_table))
+    fu = O.encode(x, u, og)
+    rhs = float(np.sum(fu * gf))
+    scale = float(np.sum(O.encode(x, np.abs(u), og) * np.abs(gf)))
+    assert abs(lhs - rhs) <= RTOL_GRAD * scale
