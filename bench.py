@@ -1,0 +1,290 @@
+#!/usr/bin/env python3
+"""Throughput of the DASH 4D hash deformation path (forward + backward) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-probes]
+
+Workload: the paper-shaped scene -- 200k dynamic Gaussians in a 64-cluster cloud,
+timestamps on a 300-frame grid, L = 16 levels, F = 2, T = 2^19 rows per hashed
+level, spatial resolutions 16 -> 2048 and temporal 16 -> 150 (Eq. 7), decoder
+32 -> 64 -> 64 -> 10.  Synthetic inputs (seed 0) stand in for the paper's scenes.
+
+One step = zero the table / decoder gradients, encode (Eqs. 8-9), decode, decoder
+backward, table scatter: every kernel of the path, inputs resident in HBM.  The
+timed region is bracketed by device synchronisation; HIP events on the stream the
+kernels run on split it per kernel.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "4D-hash deform queries/s fwd+bwd (N=200k, L=16, T=2^19), BF16 vs FP32"
+HBM_PEAK_GBPS = 8000.0
+KERNEL_SOURCES = ("encode.hip", "h4d_device.h", "mlp.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-probes", action="store_true", help="skip the roofline probes")
+    ap.add_argument("--cpu-sample", type=int, default=40000, help="queries the CPU oracle is timed on")
+    return ap.parse_args()
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2507_19141_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+class Path:
+    """Device buffers and the step of one form (fp32 or bf16) of the workload."""
+
+    def __init__(self, torch, _lib, synth, form: str):
+        self.torch, self.L_, self.form = torch, _lib, form
+        w = synth.PAPER_SCENE
+        self.w = w
+        rng, x = synth.scene_inputs(w.n, 0)
+        rs = _lib.h4d_grid_schedule(w.L, *w.space)
+        rt = _lib.h4d_grid_schedule(w.L, *w.time)
+        self.g = _lib.h4d_grid_init(w.L, w.F, rs, rt, w.T)
+        self.m = _lib.mlp_shape(w.n_in)
+        E, F, n = self.g.E, w.F, w.n
+        table = synth.table_init(E, F, rng)
+        params = synth.decoder_params(w.n_in, rng)
+        gd = synth.upstream(n, 10, rng)
+        dev = lambda a: torch.from_numpy(a).cuda()
+        self.n, self.E = n, E
+        self.xyzt = dev(x)
+        self.table32 = dev(table)
+        self.params32 = dev(params)
+        self.d_delta = dev(gd)
+        self.feat = torch.empty((w.L, n, F), device="cuda")
+        self.delta = torch.empty((n, 10), device="cuda")
+        self.d_feat = torch.empty((w.L, n, F), device="cuda")
+        self.d_table = torch.zeros((E, F), device="cuda")
+        self.d_params = torch.zeros(params.size, device="cuda")
+        self.dt = _lib.BF16 if form == "bf16" else _lib.F32
+        self.ws_bytes = _lib.deform_mlp_workspace_bytes(self.m, self.dt, n)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+        if form == "bf16":
+            self.table_lo = torch.empty(E * F, dtype=torch.int16, device="cuda")
+            self.params_lo = torch.empty(params.size, dtype=torch.int16, device="cuda")
+            self.counter = torch.zeros(1, dtype=torch.int32, device="cuda")
+            self.loss_scale = 4096.0
+        self.names = (["cast"] if form == "bf16" else []) + ["encode", "decode", "decode_bwd", "scatter"]
+
+    def step(self, ev=None):
+        L_, t = self.L_, self.torch
+        LM, F = L_.LEVEL_MAJOR, self.w.F
+        k = 0
+
+        def mark():
+            nonlocal k
+            if ev is not None:
+                ev[k].record()
+            k += 1
+        self.d_table.zero_()
+        self.d_params.zero_()
+        mark()
+        if self.form == "bf16":
+            # precision glue: BF16 copies of the FP32 masters, loss-scaled backward, overflow count
+            L_.h4d_cast_bf16(self.table32, self.table_lo, self.E * F)
+            L_.h4d_cast_bf16(self.params32, self.params_lo, self.params32.numel())
+            self.counter.zero_()
+            mark()
+            table, params, S = self.table_lo, self.params_lo, self.loss_scale
+        else:
+            table, params, S = self.table32, self.params32, 1.0
+        L_.hash4d_encode(self.g, self.dt, table, self.xyzt, self.n, self.feat, LM)
+        mark()
+        L_.deform_mlp_forward(self.m, self.dt, params, self.feat, self.n, self.delta, LM, F)
+        mark()
+        L_.deform_mlp_backward(self.m, self.dt, params, self.feat, self.n, self.d_delta, S, 1.0 / S, self.d_feat,
+                               self.d_params, self.ws, self.ws_bytes, LM, F)
+        mark()
+        L_.hash4d_encode_backward(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0 / S, self.d_table, LM)
+        if self.form == "bf16":
+            L_.h4d_count_nonfinite(self.d_table, self.E * F, self.counter)
+            L_.h4d_count_nonfinite(self.d_params, self.d_params.numel(), self.counter)
+        mark()
+
+    def run(self, steps: int, warmup: int):
+        t = self.torch
+        for _ in range(warmup):
+            self.step()
+        nev = len(self.names) + 1
+        evs = [[t.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(steps)]
+        t.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            self.step(evs[s])
+        t.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = {name: 0.0 for name in self.names}
+        for s in range(steps):
+            for i, name in enumerate(self.names):
+                per[name] += evs[s][i].elapsed_time(evs[s][i + 1])
+        per = {k: v / steps for k, v in per.items()}
+        gpu_ms = evs[0][0].elapsed_time(evs[-1][-1]) / steps
+        return wall, gpu_ms, per
+
+
+def algorithmic_bytes(L, F, table_bytes, out=10):
+    """Bytes per query each kernel must move: every corner row read or updated once
+    (16 L per query), features read/written once, inputs and outputs once."""
+    feat = L * F * 4
+    return {
+        "encode": 16 + 16 * L * F * table_bytes + feat,
+        "decode": feat + out * 4,
+        "decode_bwd": feat + out * 4 + feat,
+        "scatter": 16 + feat + 16 * L * F * 4,
+    }
+
+
+def probes(torch, _lib, E, F, n_loads, reps=5):
+    """Random-gather, random-atomic and copy ceilings at the workload's footprint."""
+    out = {}
+    buf = torch.rand((E, F), device="cuda")
+    sink = torch.zeros(1, device="cuda")
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(reps):
+            fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps / 1e3
+    t = timed(lambda: _lib.h4d_probe_gather(buf, E, 8, n_loads, 7, sink))
+    out["gather8_GBps"] = n_loads * 8 / t / 1e9
+    t = timed(lambda: _lib.h4d_probe_gather(buf, 2 * E, 4, n_loads, 7, sink))
+    out["gather4_GBps"] = n_loads * 4 / t / 1e9
+    t = timed(lambda: _lib.h4d_probe_scatter(buf, E, n_loads, 9))
+    out["scatter8_GBps"] = n_loads * 8 / t / 1e9
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, device="cuda")
+    dst = torch.empty_like(src)
+    t = timed(lambda: _lib.h4d_probe_copy(src, dst, nbytes))
+    out["copy_GBps"] = 2 * nbytes / t / 1e9
+    out["footprint_MiB"] = E * F * 4 / 2 ** 20
+    out["n_loads"] = n_loads
+    del buf, src, dst
+    return out
+
+
+def cpu_baseline(sample: int):
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hash4d_oracle as O
+    from paper_2507_19141_amd import synth
+    w = synth.PAPER_SCENE
+    rng, x = synth.scene_inputs(w.n, 0)
+    g = O.make_grid(w.L, w.F, O.level_resolutions(*w.space, w.L), O.level_resolutions(*w.time, w.L), w.T)
+    table = synth.table_init(g.E, w.F, rng)
+    params = synth.decoder_params(w.n_in, rng)
+    gd = synth.upstream(w.n, 10, rng)
+    xs, gs = x[:sample], gd[:sample]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.deform_forward(xs, table, g, params)
+        O.deform_backward(xs, table, g, params, gs)
+        dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample} of the {w.n} clustered queries, full tables; FP64 oracle forward "
+                      f"(f_h, delta) + backward (d_table, d_params) in {dt:.1f} s, 1 thread"}
+
+
+def traffic_record(dominant: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken
+    for the current kernel sources; None otherwise."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != source_hash():
+        return None
+    k = rec.get("kernels", {}).get(dominant)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
+                                   "(the multi-GPU sharding is described, not built)"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2507_19141_amd import _lib, synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    _lib.load()
+
+    fp32 = Path(torch, _lib, synth, "fp32")
+    wall, gpu_ms, per = fp32.run(args.steps, args.warmup)
+    n = fp32.n
+    ms_per_step = wall * 1e3 / args.steps
+    value = n * args.steps / wall
+    ab = algorithmic_bytes(fp32.w.L, fp32.w.F, 4)
+    dominant = max(per, key=per.get)
+    achieved = ab[dominant] * n / (per[dominant] / 1e3) / 1e9
+    traffic = traffic_record(dominant)
+    result = {
+        "metric": METRIC, "value": value, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "deform-200k-clustered-L16F2T2^19 fwd+bwd", "n": n, "L": 16, "F": 2, "T": 1 << 19,
+                   "res_s": "16->2048", "res_t": "16->150", "decoder": "32-64-64-10", "form": "fp32"},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "algorithmic_bytes_per_query": ab[dominant], "queries_per_launch": n},
+        "kernels_ms": per,
+        "gpu_ms_per_step": gpu_ms,
+    }
+    del fp32
+    torch.cuda.empty_cache()
+    bf = Path(torch, _lib, synth, "bf16")
+    wall_b, gpu_b, per_b = bf.run(args.steps, args.warmup)
+    result["forms"] = {"bf16": {"value": n * args.steps / wall_b, "ms_per_step": wall_b * 1e3 / args.steps,
+                                "kernels_ms": per_b, "loss_scale": bf.loss_scale}}
+    del bf
+    torch.cuda.empty_cache()
+    if not args.no_probes:
+        w = synth.PAPER_SCENE
+        E = _lib.h4d_grid_init(w.L, w.F, _lib.h4d_grid_schedule(w.L, *w.space),
+                               _lib.h4d_grid_schedule(w.L, *w.time), w.T).E
+        pr = probes(torch, _lib, E, w.F, n * 16 * w.L)
+        result["probes"] = pr
+        # step-level fraction of the probe ceilings (gathers at the random-gather rate,
+        # scatter at the random-atomic rate, everything else at the copy rate)
+        L, F = w.L, w.F
+        gather_b, scatter_b = 16 * L * F * 4, 16 * L * F * 4
+        stream_b = sum(ab.values()) - gather_b - scatter_b
+        t_roof = n * (gather_b / (pr["gather8_GBps"] * 1e9) + scatter_b / (pr["scatter8_GBps"] * 1e9)
+                      + stream_b / (pr["copy_GBps"] * 1e9))
+        result["achievable_frac"] = t_roof / (gpu_ms / 1e3)
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -49,6 +49,11 @@ typedef enum {
 } h4d_dtype;
 
 typedef enum {
+    H4D_QUERY_MAJOR = 0,  /* features [n, L F]: feature l F + f of query q at q L F + l F + f */
+    H4D_LEVEL_MAJOR = 1   /* features [L, n, F]: at l n F + q F + f (coalesced per level) */
+} h4d_layout;
+
+typedef enum {
     H4D_SCHEDULE_GEOMETRIC = 0, /* Eq. 7: N_l = floor(N_min b^l), b = (N_max/N_min)^(1/(L-1)) */
     H4D_SCHEDULE_DOUBLING = 1   /* N_l = min(N_min 2^l, N_max) */
 } h4d_schedule;
@@ -76,7 +81,7 @@ typedef struct {
  * array in the order W1[hidden, in], b1[hidden], W2[hidden, hidden], b2[hidden],
  * W3[out, hidden], b3[out], weights row-major [out, in]. */
 typedef struct {
-    int32_t in;       /* 4..128, multiple of 4 (multiple of 8 for BF16) */
+    int32_t in;       /* 8, 16, 32 or 64 */
     int32_t hidden;   /* must be 64 */
     int32_t out;      /* 1..16 */
 } h4d_mlp;
@@ -111,19 +116,20 @@ int64_t h4d_grid_rows(const h4d_grid* g);
  * take the 16 corners of the hypervoxel, index them (dense or hashed), gather F
  * features per corner and interpolate quadrilinearly.
  *   table   [E, F] of table_dt (F32, BF16 bit patterns, or F64)
- *   feat    [n, L F], feature l F + f; FP32 for F32/BF16 tables, FP64 for F64.
+ *   feat    n L F values in `layout`; FP32 for F32/BF16 tables, FP64 for F64.
  * Written, not accumulated.  Deterministic (no atomics). */
 h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* table,
-                         const float* xyzt, int64_t n, void* feat, void* stream);
+                         const float* xyzt, int64_t n, h4d_layout layout, void* feat, void* stream);
 
 /* Backward of hash4d_encode with respect to the table (the exact transpose of the
  * interpolation in Eq. 9): d_table[row_c, f] += grad_scale * w_c * d_feat[q, l F + f]
  * over every query, level and corner.  Corners and weights are recomputed from
  * xyzt.  grad_dt F32: d_feat and d_table are FP32; F64: both FP64.
- *   d_feat  [n, L F]     d_table [E, F] (+=)
+ *   d_feat  n L F values in `layout`     d_table [E, F] (+=)
  * Uses device atomics: the summation order, hence the last bits, vary run to run. */
 h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
-                                  const void* d_feat, float grad_scale, void* d_table, void* stream);
+                                  h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
+                                  void* stream);
 
 /* Test hook: the table row (level offset included) and FP32 weight of the 16
  * corners of every query and level.  Corner c is upper along x, y, z, t iff bit
@@ -131,6 +137,93 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
  *   rows [n, L, 16] int32      w [n, L, 16] FP32 (either may be NULL) */
 h4d_status hash4d_corner_indices(const h4d_grid* g, const float* xyzt, int64_t n,
                                  int32_t* rows, float* w, void* stream);
+
+/* ----------------------------------------------------- precision form ---- */
+
+/* dst[i] = BF16 (round to nearest even, NaN kept quiet) of the FP32 master src[i],
+ * as uint16 bit patterns: the per-step copy of tables or decoder parameters the
+ * BF16 form reads.  count elements; dst may not overlap src. */
+h4d_status h4d_cast_bf16(const float* src, uint16_t* dst, int64_t count, void* stream);
+
+/* *counter += number of NaN or Inf values in p[0, count) (the overflow check of
+ * dynamic loss scaling).  The caller zeroes *counter (device int32). */
+h4d_status h4d_count_nonfinite(const float* p, int64_t count, int32_t* counter, void* stream);
+
+/* ------------------------------------------------------------- decoder ---- */
+
+/* Bytes of workspace deform_mlp_backward needs for n queries (split-N partial
+ * weight gradients: one row of P parameters per persistent block).  0 if *m is
+ * invalid. */
+size_t deform_mlp_workspace_bytes(const h4d_mlp* m, h4d_dtype dt, int64_t n);
+
+/* Decoder forward (Section 4.2: the trunk phi_d of Eq. 9, then the position,
+ * rotation and scale heads): h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2),
+ * delta = W3 h2 + b3, computed on MFMA tiles of 16 queries.
+ *   dt      F32: params/feat/out FP32.  BF16: params BF16 bit patterns, feat and out
+ *           FP32, activations rounded to BF16 for the MFMA, FP32 accumulation.
+ *           F64: everything FP64.
+ *   feat    [n, in] (H4D_QUERY_MAJOR) or [in / F, n, F] (H4D_LEVEL_MAJOR, F in {1,2,4,8}
+ *           dividing in; F is ignored for query-major)
+ *   out     [n, out] (written) */
+h4d_status deform_mlp_forward(const h4d_mlp* m, h4d_dtype dt, const void* params, const void* feat, int64_t n,
+                              h4d_layout layout, int32_t F, void* out, void* stream);
+
+/* Decoder backward: gradients of <delta, loss_scale * d_out> (ReLU passes gradient
+ * where its input is > 0).  d_feat [n, in] is WRITTEN as grad_scale times the
+ * feature gradient; d_params (FP32, FP64 for F64) ACCUMULATES grad_scale times the
+ * parameter gradient.  The forward is recomputed from feat; weight gradients are
+ * reduced over queries per persistent block into `workspace` (device, at least
+ * deform_mlp_workspace_bytes) and then summed by a second kernel, so the result is
+ * deterministic for a given n.
+ *   d_out [n, out] (FP32, FP64 for F64); feat and d_feat in (layout, F) as in
+ *   deform_mlp_forward. */
+h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* params, const void* feat, int64_t n,
+                               h4d_layout layout, int32_t F, const void* d_out, float loss_scale, float grad_scale,
+                               void* d_feat, void* d_params, void* workspace, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------- deformation path ---- */
+
+/* Workspace of hash4d_deform_backward: decoder partials plus the [L, n, F]
+ * feature gradient.  0 if the arguments are invalid. */
+size_t hash4d_deform_workspace_bytes(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, int64_t n);
+
+/* Whole forward of the deformation field for n dynamic Gaussians at their
+ * timestamps: the encoder G_4D (Eqs. 8-9) followed by the decoder (delta of
+ * position, rotation and scale, the increments of Eq. 10).
+ *   dt      F32: FP32 table and params.  BF16: BF16 table and params (bit patterns),
+ *           FP32 features.  F64: FP64 everything.
+ *   feat    [L, n, F] level-major (FP32; FP64 for F64), WRITTEN: the encoder output,
+ *           kept for the backward.  m->in must equal L F.
+ *   delta   [n, m->out] (FP32; FP64 for F64), WRITTEN. */
+h4d_status hash4d_deform_forward(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, const void* table,
+                                 const void* params, const float* xyzt, int64_t n, void* feat, void* delta,
+                                 void* stream);
+
+/* Whole backward of the deformation field: decoder backward from d_delta (scaled
+ * by loss_scale on load), then the table scatter of Eq. 9's transpose.  d_table
+ * [E, F] and d_params ACCUMULATE grad_scale times their gradients (FP32; FP64 for
+ * F64).  feat is the buffer hash4d_deform_forward wrote.  workspace: device, at
+ * least hash4d_deform_workspace_bytes. */
+h4d_status hash4d_deform_backward(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, const void* params,
+                                  const float* xyzt, int64_t n, const void* feat, const void* d_delta,
+                                  float loss_scale, float grad_scale, void* d_table, void* d_params,
+                                  void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------- roofline probes ---- */
+
+/* Measurement kernels for the ceilings the encoder is compared against (not part
+ * of the method).  Row numbers are uniform pseudo-random, from a counter-based
+ * hash of the load index and `seed`.
+ * gather:  n_loads loads of one row_bytes (4 or 8) row from table[rows]; 16 loads
+ *          in flight per thread.  sink: device float, written only in a case that
+ *          practically never occurs (it keeps the loads alive).
+ * scatter: n_updates updates, each adding 1.0f with a device atomic to both FP32
+ *          values of one random 8-byte row of table[rows][2].
+ * copy:    bytes (multiple of 16) copied src -> dst with 16-byte vector accesses. */
+h4d_status h4d_probe_gather(const void* table, int64_t rows, int32_t row_bytes, int64_t n_loads, uint32_t seed,
+                            float* sink, void* stream);
+h4d_status h4d_probe_scatter(float* table, int64_t rows, int64_t n_updates, uint32_t seed, void* stream);
+h4d_status h4d_probe_copy(const void* src, void* dst, int64_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

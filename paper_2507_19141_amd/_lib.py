@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libhash4d.so")
 
 MAX_LEVELS = 32
 F32, BF16, F64 = 0, 1, 2
+QUERY_MAJOR, LEVEL_MAJOR = 0, 1
 SCHEDULE_GEOMETRIC, SCHEDULE_DOUBLING = 0, 1
 STATUS = {0: "H4D_OK", -1: "H4D_EINVAL", -2: "H4D_EUNSUPPORTED", -3: "H4D_EHIP", -4: "H4D_ENOPLAN"}
 
@@ -60,9 +61,20 @@ SIGNATURES = {
     "h4d_grid_schedule": (_I32, [_I32, _I32, _I32, _I32, ctypes.POINTER(_I32)]),
     "h4d_grid_init": (_I32, [_GP, _I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _I64]),
     "h4d_grid_rows": (_I64, [_GP]),
-    "hash4d_encode": (_I32, [_GP, _I32, _P, _P, _I64, _P, _P]),
-    "hash4d_encode_backward": (_I32, [_GP, _I32, _P, _I64, _P, _F32, _P, _P]),
+    "hash4d_encode": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _P]),
+    "hash4d_encode_backward": (_I32, [_GP, _I32, _P, _I64, _I32, _P, _F32, _P, _P]),
     "hash4d_corner_indices": (_I32, [_GP, _P, _I64, _P, _P, _P]),
+    "h4d_cast_bf16": (_I32, [_P, _P, _I64, _P]),
+    "h4d_count_nonfinite": (_I32, [_P, _I64, _P, _P]),
+    "deform_mlp_workspace_bytes": (_SZ, [_MP, _I32, _I64]),
+    "deform_mlp_forward": (_I32, [_MP, _I32, _P, _P, _I64, _I32, _I32, _P, _P]),
+    "deform_mlp_backward": (_I32, [_MP, _I32, _P, _P, _I64, _I32, _I32, _P, _F32, _F32, _P, _P, _P, _SZ, _P]),
+    "hash4d_deform_workspace_bytes": (_SZ, [_GP, _MP, _I32, _I64]),
+    "hash4d_deform_forward": (_I32, [_GP, _MP, _I32, _P, _P, _P, _I64, _P, _P, _P]),
+    "hash4d_deform_backward": (_I32, [_GP, _MP, _I32, _P, _P, _I64, _P, _P, _F32, _F32, _P, _P, _P, _SZ, _P]),
+    "h4d_probe_gather": (_I32, [_P, _I64, _I32, _I64, ctypes.c_uint32, _P, _P]),
+    "h4d_probe_scatter": (_I32, [_P, _I64, _I64, ctypes.c_uint32, _P]),
+    "h4d_probe_copy": (_I32, [_P, _P, _I64, _P]),
 }
 
 _lib = None
@@ -136,21 +148,88 @@ def h4d_grid_rows(g: Grid) -> int:
 
 
 # --------------------------------------------------------------- encoder ----
-def hash4d_encode(g: Grid, table_dt: int, table, xyzt, n: int, feat, stream=None) -> None:
-    _check("hash4d_encode", load().hash4d_encode(ctypes.byref(g), table_dt, ptr(table), ptr(xyzt), n, ptr(feat),
-                                                 stream_handle(stream)))
+def hash4d_encode(g: Grid, table_dt: int, table, xyzt, n: int, feat, layout: int = QUERY_MAJOR,
+                  stream=None) -> None:
+    _check("hash4d_encode", load().hash4d_encode(ctypes.byref(g), table_dt, ptr(table), ptr(xyzt), n, layout,
+                                                 ptr(feat), stream_handle(stream)))
 
 
 def hash4d_encode_backward(g: Grid, grad_dt: int, xyzt, n: int, d_feat, grad_scale: float, d_table,
-                           stream=None) -> None:
+                           layout: int = QUERY_MAJOR, stream=None) -> None:
     _check("hash4d_encode_backward",
-           load().hash4d_encode_backward(ctypes.byref(g), grad_dt, ptr(xyzt), n, ptr(d_feat), grad_scale,
+           load().hash4d_encode_backward(ctypes.byref(g), grad_dt, ptr(xyzt), n, layout, ptr(d_feat), grad_scale,
                                          ptr(d_table), stream_handle(stream)))
 
 
 def hash4d_corner_indices(g: Grid, xyzt, n: int, rows, w, stream=None) -> None:
     _check("hash4d_corner_indices", load().hash4d_corner_indices(ctypes.byref(g), ptr(xyzt), n, ptr(rows), ptr(w),
                                                                  stream_handle(stream)))
+
+
+# ------------------------------------------------------- precision form ----
+def h4d_cast_bf16(src, dst, count: int, stream=None) -> None:
+    _check("h4d_cast_bf16", load().h4d_cast_bf16(ptr(src), ptr(dst), count, stream_handle(stream)))
+
+
+def h4d_count_nonfinite(p, count: int, counter, stream=None) -> None:
+    _check("h4d_count_nonfinite", load().h4d_count_nonfinite(ptr(p), count, ptr(counter), stream_handle(stream)))
+
+
+# --------------------------------------------------------------- decoder ----
+def mlp_shape(n_in: int, hidden: int = 64, out: int = 10) -> Mlp:
+    return Mlp(n_in, hidden, out)
+
+
+def deform_mlp_workspace_bytes(m: Mlp, dt: int, n: int) -> int:
+    return int(load().deform_mlp_workspace_bytes(ctypes.byref(m), dt, n))
+
+
+def deform_mlp_forward(m: Mlp, dt: int, params, feat, n: int, out, layout: int = QUERY_MAJOR, F: int = 0,
+                       stream=None) -> None:
+    _check("deform_mlp_forward", load().deform_mlp_forward(ctypes.byref(m), dt, ptr(params), ptr(feat), n, layout, F,
+                                                           ptr(out), stream_handle(stream)))
+
+
+def deform_mlp_backward(m: Mlp, dt: int, params, feat, n: int, d_out, loss_scale: float, grad_scale: float,
+                        d_feat, d_params, workspace, ws_bytes: int, layout: int = QUERY_MAJOR, F: int = 0,
+                        stream=None) -> None:
+    _check("deform_mlp_backward",
+           load().deform_mlp_backward(ctypes.byref(m), dt, ptr(params), ptr(feat), n, layout, F, ptr(d_out),
+                                      loss_scale, grad_scale, ptr(d_feat), ptr(d_params), ptr(workspace), ws_bytes,
+                                      stream_handle(stream)))
+
+
+# ------------------------------------------------------ deformation path ----
+def hash4d_deform_workspace_bytes(g: Grid, m: Mlp, dt: int, n: int) -> int:
+    return int(load().hash4d_deform_workspace_bytes(ctypes.byref(g), ctypes.byref(m), dt, n))
+
+
+def hash4d_deform_forward(g: Grid, m: Mlp, dt: int, table, params, xyzt, n: int, feat, delta, stream=None) -> None:
+    _check("hash4d_deform_forward",
+           load().hash4d_deform_forward(ctypes.byref(g), ctypes.byref(m), dt, ptr(table), ptr(params), ptr(xyzt), n,
+                                        ptr(feat), ptr(delta), stream_handle(stream)))
+
+
+def hash4d_deform_backward(g: Grid, m: Mlp, dt: int, params, xyzt, n: int, feat, d_delta, loss_scale: float,
+                           grad_scale: float, d_table, d_params, workspace, ws_bytes: int, stream=None) -> None:
+    _check("hash4d_deform_backward",
+           load().hash4d_deform_backward(ctypes.byref(g), ctypes.byref(m), dt, ptr(params), ptr(xyzt), n, ptr(feat),
+                                         ptr(d_delta), loss_scale, grad_scale, ptr(d_table), ptr(d_params),
+                                         ptr(workspace), ws_bytes, stream_handle(stream)))
+
+
+# -------------------------------------------------------- roofline probes ----
+def h4d_probe_gather(table, rows: int, row_bytes: int, n_loads: int, seed: int, sink, stream=None) -> None:
+    _check("h4d_probe_gather", load().h4d_probe_gather(ptr(table), rows, row_bytes, n_loads, seed, ptr(sink),
+                                                       stream_handle(stream)))
+
+
+def h4d_probe_scatter(table, rows: int, n_updates: int, seed: int, stream=None) -> None:
+    _check("h4d_probe_scatter", load().h4d_probe_scatter(ptr(table), rows, n_updates, seed, stream_handle(stream)))
+
+
+def h4d_probe_copy(src, dst, nbytes: int, stream=None) -> None:
+    _check("h4d_probe_copy", load().h4d_probe_copy(ptr(src), ptr(dst), nbytes, stream_handle(stream)))
 
 
 def hip_runtimes_loaded() -> list:

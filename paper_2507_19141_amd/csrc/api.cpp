@@ -97,6 +97,21 @@ static h4d_status check_dtype(h4d_dtype dt) {
     return H4D_OK;
 }
 
+static h4d_status check_mlp(const h4d_mlp* m, h4d_dtype dt) {
+    if (!m) return fail(H4D_EINVAL, "mlp pointer is NULL");
+    if (m->hidden != H4D_HIDDEN) return fail(H4D_EINVAL, "mlp: hidden=%d, only %d is built", m->hidden, H4D_HIDDEN);
+    if (m->out < 1 || m->out > H4D_MAX_OUT) return fail(H4D_EINVAL, "mlp: out=%d outside 1..%d", m->out, H4D_MAX_OUT);
+    if (m->in != 8 && m->in != 16 && m->in != 32 && m->in != 64)
+        return fail(H4D_EUNSUPPORTED, "mlp: in=%d, built widths are 8, 16, 32, 64", m->in);
+    return check_dtype(dt);
+}
+
+static size_t deform_ws(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, int64_t n) {
+    const size_t el = dt == H4D_F64 ? sizeof(double) : sizeof(float);
+    const size_t a = (mlp_workspace_bytes(dt, m->in, m->out, (int)n) + 255) / 256 * 256;
+    return a + (size_t)n * g->L * g->F * el;
+}
+
 }  // namespace h4d
 
 using namespace h4d;
@@ -175,30 +190,49 @@ int64_t h4d_grid_rows(const h4d_grid* g) {
     return g->offset[g->L];
 }
 
+// Strides of feature (level l, query q): [n, L F] or [L, n, F].
+static h4d_status feat_strides(h4d_layout layout, int64_t n, int L, int F, int64_t* ls, int64_t* qs) {
+    if (layout == H4D_QUERY_MAJOR) {
+        *ls = F;
+        *qs = (int64_t)L * F;
+    } else if (layout == H4D_LEVEL_MAJOR) {
+        *ls = n * F;
+        *qs = F;
+    } else {
+        return fail(H4D_EINVAL, "unknown layout %d", (int)layout);
+    }
+    if (n * (int64_t)L * F > kMaxN) return fail(H4D_EINVAL, "n L F exceeds 2^31-1 features");
+    return H4D_OK;
+}
+
 h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* table, const float* xyzt, int64_t n,
-                         void* feat, void* stream) {
+                         h4d_layout layout, void* feat, void* stream) {
     g_last_error.clear();
     h4d_status st;
+    int64_t ls, qs;
     if ((st = check_grid(g)) || (st = check_dtype(table_dt)) || (st = check_xyzt(xyzt, n))) return st;
+    if ((st = feat_strides(layout, n, g->L, g->F, &ls, &qs))) return st;
     if (n == 0) return H4D_OK;
     if (!table || !feat) return fail(H4D_EINVAL, "table or feat is NULL");
     const DevGrid d = to_device(*g);
-    return hip_status(launch_encode(d, table_dt, table, xyzt, (int)n, feat, g->F, (int64_t)g->L * g->F,
-                                    (hipStream_t)stream),
+    return hip_status(launch_encode(d, table_dt, table, xyzt, (int)n, feat, ls, qs, (hipStream_t)stream),
                       "hash4d_encode");
 }
 
 h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
-                                  const void* d_feat, float grad_scale, void* d_table, void* stream) {
+                                  h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
+                                  void* stream) {
     g_last_error.clear();
     h4d_status st;
+    int64_t ls, qs;
     if ((st = check_grid(g)) || (st = check_xyzt(xyzt, n))) return st;
     if (grad_dt != H4D_F32 && grad_dt != H4D_F64) return fail(H4D_EINVAL, "grad dtype must be F32 or F64");
+    if ((st = feat_strides(layout, n, g->L, g->F, &ls, &qs))) return st;
     if (n == 0) return H4D_OK;
     if (!d_feat || !d_table) return fail(H4D_EINVAL, "d_feat or d_table is NULL");
     const DevGrid d = to_device(*g);
-    return hip_status(launch_encode_backward(d, grad_dt, xyzt, (int)n, d_feat, g->F, (int64_t)g->L * g->F,
-                                             (double)grad_scale, d_table, (hipStream_t)stream),
+    return hip_status(launch_encode_backward(d, grad_dt, xyzt, (int)n, d_feat, ls, qs, (double)grad_scale, d_table,
+                                             (hipStream_t)stream),
                       "hash4d_encode_backward");
 }
 
@@ -212,6 +246,170 @@ h4d_status hash4d_corner_indices(const h4d_grid* g, const float* xyzt, int64_t n
     if (n * (int64_t)g->L * 16 > kMaxN) return fail(H4D_EINVAL, "n L 16 exceeds 2^31-1 outputs");
     const DevGrid d = to_device(*g);
     return hip_status(launch_corner_indices(d, xyzt, (int)n, rows, w, (hipStream_t)stream), "hash4d_corner_indices");
+}
+
+h4d_status h4d_cast_bf16(const float* src, uint16_t* dst, int64_t count, void* stream) {
+    g_last_error.clear();
+    if (count < 0) return fail(H4D_EINVAL, "count=%lld < 0", (long long)count);
+    if (count == 0) return H4D_OK;
+    if (!src || !dst) return fail(H4D_EINVAL, "src or dst is NULL");
+    return hip_status(launch_cast_bf16(src, dst, count, (hipStream_t)stream), "h4d_cast_bf16");
+}
+
+h4d_status h4d_count_nonfinite(const float* p, int64_t count, int32_t* counter, void* stream) {
+    g_last_error.clear();
+    if (count < 0) return fail(H4D_EINVAL, "count=%lld < 0", (long long)count);
+    if (count == 0) return H4D_OK;
+    if (!p || !counter) return fail(H4D_EINVAL, "p or counter is NULL");
+    return hip_status(launch_count_nonfinite(p, count, counter, (hipStream_t)stream), "h4d_count_nonfinite");
+}
+
+h4d_status h4d_probe_gather(const void* table, int64_t rows, int32_t row_bytes, int64_t n_loads, uint32_t seed,
+                            float* sink, void* stream) {
+    g_last_error.clear();
+    if (rows < 1 || rows > 0xffffffffLL) return fail(H4D_EINVAL, "rows=%lld outside 1..2^32-1", (long long)rows);
+    if (row_bytes != 4 && row_bytes != 8) return fail(H4D_EINVAL, "row_bytes must be 4 or 8");
+    if (n_loads < 0 || n_loads > ((int64_t)1 << 40)) return fail(H4D_EINVAL, "n_loads out of range");
+    if (n_loads == 0) return H4D_OK;
+    if (!table || !sink) return fail(H4D_EINVAL, "table or sink is NULL");
+    if (((uintptr_t)table) & 7u) return fail(H4D_EINVAL, "table is not 8-byte aligned");
+    return hip_status(launch_probe_gather(table, (uint32_t)rows, row_bytes, n_loads, seed, sink, (hipStream_t)stream),
+                      "h4d_probe_gather");
+}
+
+h4d_status h4d_probe_scatter(float* table, int64_t rows, int64_t n_updates, uint32_t seed, void* stream) {
+    g_last_error.clear();
+    if (rows < 1 || rows > 0xffffffffLL) return fail(H4D_EINVAL, "rows=%lld outside 1..2^32-1", (long long)rows);
+    if (n_updates < 0 || n_updates > ((int64_t)1 << 40)) return fail(H4D_EINVAL, "n_updates out of range");
+    if (n_updates == 0) return H4D_OK;
+    if (!table) return fail(H4D_EINVAL, "table is NULL");
+    return hip_status(launch_probe_scatter(table, (uint32_t)rows, n_updates, seed, (hipStream_t)stream),
+                      "h4d_probe_scatter");
+}
+
+h4d_status h4d_probe_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+    g_last_error.clear();
+    if (bytes < 0 || (bytes & 15)) return fail(H4D_EINVAL, "bytes must be a non-negative multiple of 16");
+    if (bytes == 0) return H4D_OK;
+    if (!src || !dst || ((((uintptr_t)src) | ((uintptr_t)dst)) & 15u))
+        return fail(H4D_EINVAL, "src/dst NULL or not 16-byte aligned");
+    return hip_status(launch_probe_copy(src, dst, bytes, (hipStream_t)stream), "h4d_probe_copy");
+}
+
+size_t deform_mlp_workspace_bytes(const h4d_mlp* m, h4d_dtype dt, int64_t n) {
+    if (check_mlp(m, dt) != H4D_OK || n < 0 || n > kMaxN) return 0;
+    return mlp_workspace_bytes(dt, m->in, m->out, (int)n);
+}
+
+// Feature strides of the decoder input for (layout, F); F = 1 for query-major.
+static h4d_status mlp_strides(const h4d_mlp* m, int64_t n, h4d_layout layout, int32_t F, int* Fk, int64_t* ls,
+                              int64_t* qs) {
+    if (n < 0 || n > kMaxN) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-1", (long long)n);
+    if ((int64_t)n * m->in > kMaxN) return fail(H4D_EINVAL, "n in exceeds 2^31-1 features");
+    if (layout == H4D_QUERY_MAJOR) {
+        *Fk = 1;
+        *ls = 1;
+        *qs = m->in;
+        return H4D_OK;
+    }
+    if (layout != H4D_LEVEL_MAJOR) return fail(H4D_EINVAL, "unknown layout %d", (int)layout);
+    if (!valid_F(F) || m->in % F) return fail(H4D_EINVAL, "level-major F=%d must be 1, 2, 4 or 8 and divide in", F);
+    *Fk = F;
+    *ls = n * F;
+    *qs = F;
+    return H4D_OK;
+}
+
+h4d_status deform_mlp_forward(const h4d_mlp* m, h4d_dtype dt, const void* params, const void* feat, int64_t n,
+                              h4d_layout layout, int32_t F, void* out, void* stream) {
+    g_last_error.clear();
+    h4d_status st;
+    int Fk;
+    int64_t ls, qs;
+    if ((st = check_mlp(m, dt)) || (st = mlp_strides(m, n, layout, F, &Fk, &ls, &qs))) return st;
+    if (n == 0) return H4D_OK;
+    if (!params || !feat || !out) return fail(H4D_EINVAL, "params, feat or out is NULL");
+    return hip_status(launch_mlp_forward(dt, m->in, m->out, params, feat, Fk, ls, qs, (int)n, out,
+                                         (hipStream_t)stream),
+                      "deform_mlp_forward");
+}
+
+h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* params, const void* feat, int64_t n,
+                               h4d_layout layout, int32_t F, const void* d_out, float loss_scale, float grad_scale,
+                               void* d_feat, void* d_params, void* workspace, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    h4d_status st;
+    int Fk;
+    int64_t ls, qs;
+    if ((st = check_mlp(m, dt)) || (st = mlp_strides(m, n, layout, F, &Fk, &ls, &qs))) return st;
+    if (n == 0) return H4D_OK;
+    if (!params || !feat || !d_out || !d_feat || !d_params) return fail(H4D_EINVAL, "NULL data pointer");
+    const size_t need = mlp_workspace_bytes(dt, m->in, m->out, (int)n);
+    if (!workspace || ws_bytes < need)
+        return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    return hip_status(launch_mlp_backward(dt, m->in, m->out, params, feat, Fk, ls, qs, (int)n, d_out, loss_scale,
+                                          grad_scale, grad_scale, d_feat, ls, qs, d_params, workspace,
+                                          (hipStream_t)stream),
+                      "deform_mlp_backward");
+}
+
+size_t hash4d_deform_workspace_bytes(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, int64_t n) {
+    if (check_grid(g) != H4D_OK || check_mlp(m, dt) != H4D_OK || n < 0 || n > kMaxN) return 0;
+    return deform_ws(g, m, dt, n);
+}
+
+static h4d_status check_deform(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, const float* xyzt, int64_t n) {
+    h4d_status st;
+    if ((st = check_grid(g)) || (st = check_mlp(m, dt)) || (st = check_xyzt(xyzt, n))) return st;
+    if (m->in != g->L * g->F)
+        return fail(H4D_EINVAL, "decoder input width %d != L F = %d", m->in, g->L * g->F);
+    if ((int64_t)n * g->L * g->F > kMaxN) return fail(H4D_EINVAL, "n L F exceeds 2^31-1 features");
+    return H4D_OK;
+}
+
+h4d_status hash4d_deform_forward(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, const void* table,
+                                 const void* params, const float* xyzt, int64_t n, void* feat, void* delta,
+                                 void* stream) {
+    g_last_error.clear();
+    h4d_status st;
+    if ((st = check_deform(g, m, dt, xyzt, n))) return st;
+    if (n == 0) return H4D_OK;
+    if (!table || !params || !feat || !delta) return fail(H4D_EINVAL, "NULL data pointer");
+    const DevGrid d = to_device(*g);
+    const hipStream_t s = (hipStream_t)stream;
+    const int64_t ls = n * g->F, qs = g->F;
+    if ((st = hip_status(launch_encode(d, dt, table, xyzt, (int)n, feat, ls, qs, s), "hash4d_deform_forward/encode")))
+        return st;
+    return hip_status(launch_mlp_forward(dt, m->in, m->out, params, feat, g->F, ls, qs, (int)n, delta, s),
+                      "hash4d_deform_forward/decode");
+}
+
+h4d_status hash4d_deform_backward(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, const void* params,
+                                  const float* xyzt, int64_t n, const void* feat, const void* d_delta,
+                                  float loss_scale, float grad_scale, void* d_table, void* d_params,
+                                  void* workspace, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    h4d_status st;
+    if ((st = check_deform(g, m, dt, xyzt, n))) return st;
+    if (n == 0) return H4D_OK;
+    if (!params || !feat || !d_delta || !d_table || !d_params) return fail(H4D_EINVAL, "NULL data pointer");
+    const size_t need = deform_ws(g, m, dt, n);
+    if (!workspace || ws_bytes < need)
+        return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    const DevGrid d = to_device(*g);
+    const hipStream_t s = (hipStream_t)stream;
+    const int64_t ls = n * g->F, qs = g->F;
+    char* ws = static_cast<char*>(workspace);
+    const size_t part = (mlp_workspace_bytes(dt, m->in, m->out, (int)n) + 255) / 256 * 256;
+    void* d_feat = ws + part;
+    // decoder backward: d_feat keeps the loss scale, d_params gets grad_scale
+    if ((st = hip_status(launch_mlp_backward(dt, m->in, m->out, params, feat, g->F, ls, qs, (int)n, d_delta,
+                                             loss_scale, 1.0, grad_scale, d_feat, ls, qs, d_params, ws, s),
+                         "hash4d_deform_backward/decode")))
+        return st;
+    return hip_status(launch_encode_backward(d, dt == H4D_F64 ? H4D_F64 : H4D_F32, xyzt, (int)n, d_feat, ls, qs,
+                                             grad_scale, d_table, s),
+                      "hash4d_deform_backward/encode");
 }
 
 }  // extern "C"

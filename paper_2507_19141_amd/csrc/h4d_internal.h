@@ -35,4 +35,26 @@ hipError_t launch_encode_backward(const DevGrid& g, h4d_dtype grad_dt, const flo
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w,
                                  hipStream_t s);
 
+// ---- decoder launchers (mlp.hip) ----
+// Features / feature gradients are addressed as feat[(k / F) lstride + q qstride + k % F].
+size_t mlp_workspace_bytes(h4d_dtype dt, int in, int out, int n);
+hipError_t launch_mlp_forward(h4d_dtype dt, int in, int out, const void* params, const void* feat, int F,
+                              int64_t lstride, int64_t qstride, int n, void* delta, hipStream_t s);
+// d_out is multiplied by in_scale on load; d_feat is written times feat_scale;
+// d_params += param_scale * sum of the per-block partial gradients.
+hipError_t launch_mlp_backward(h4d_dtype dt, int in, int out, const void* params, const void* feat, int F,
+                               int64_t lstride, int64_t qstride, int n, const void* d_out, double in_scale,
+                               double feat_scale, double param_scale, void* d_feat, int64_t dlstride,
+                               int64_t dqstride, void* d_params, void* ws, hipStream_t s);
+
+// ---- precision helpers (precision.hip) ----
+hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s);
+hipError_t launch_count_nonfinite(const float* p, int64_t count, int32_t* counter, hipStream_t s);
+
+// ---- roofline probes (probe.hip) ----
+hipError_t launch_probe_gather(const void* table, uint32_t rows, int row_bytes, int64_t n_loads, uint32_t seed,
+                               float* sink, hipStream_t s);
+hipError_t launch_probe_scatter(float* table, uint32_t rows, int64_t n_updates, uint32_t seed, hipStream_t s);
+hipError_t launch_probe_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+
 }  // namespace h4d

@@ -1,0 +1,48 @@
+// Precision-form helpers of the BF16 path: master-to-BF16 rounding and the
+// non-finite check behind dynamic loss scaling.  Both are plain streaming kernels.
+#include "h4d_device.h"
+
+namespace h4d {
+
+constexpr int kCastBlock = 256;
+
+// dst[i] = RNE BF16 of src[i]; four elements per thread (16-byte loads, 8-byte stores).
+__global__ __launch_bounds__(kCastBlock) void k_cast_bf16(const float* __restrict__ src, uint16_t* __restrict__ dst,
+                                                          int64_t count) {
+    const int64_t i4 = ((int64_t)blockIdx.x * kCastBlock + threadIdx.x) * 4;
+    if (i4 + 3 < count && ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) == 0) {
+        const float4 v = *reinterpret_cast<const float4*>(src + i4);
+        ushort4 o;
+        o.x = f32_to_bf16(v.x); o.y = f32_to_bf16(v.y); o.z = f32_to_bf16(v.z); o.w = f32_to_bf16(v.w);
+        *reinterpret_cast<ushort4*>(dst + i4) = o;
+    } else {
+        for (int64_t i = i4; i < count && i < i4 + 4; ++i) dst[i] = f32_to_bf16(src[i]);
+    }
+}
+
+// counter += number of NaN / Inf values in p[0, count).
+__global__ __launch_bounds__(kCastBlock) void k_count_nonfinite(const float* __restrict__ p, int64_t count,
+                                                                int32_t* __restrict__ counter) {
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kCastBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kCastBlock)
+        bad += (__float_as_uint(p[i]) & 0x7f800000u) == 0x7f800000u;
+    // wavefront sum, one atomic per wavefront with a non-finite value
+    for (int s = 32; s > 0; s >>= 1) bad += __shfl_xor(bad, s, 64);
+    if ((threadIdx.x & 63) == 0 && bad) atomicAdd(counter, bad);
+}
+
+hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s) {
+    const int64_t threads = (count + 3) / 4;
+    hipLaunchKernelGGL(k_cast_bf16, dim3((unsigned)((threads + kCastBlock - 1) / kCastBlock)), dim3(kCastBlock), 0, s,
+                       src, dst, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const float* p, int64_t count, int32_t* counter, hipStream_t s) {
+    int64_t blocks = (count + kCastBlock - 1) / kCastBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)blocks), dim3(kCastBlock), 0, s, p, count, counter);
+    return hipGetLastError();
+}
+
+}  // namespace h4d

@@ -1,0 +1,98 @@
+// Roofline probes: the memory ceilings the encoder kernels are measured against.
+//  - gather:  uniformly random row loads (4 or 8 bytes) from a table of the
+//             encoder's footprint, the pattern of the corner gathers;
+//  - scatter: uniformly random 8-byte rows, each receiving two FP32 atomic adds,
+//             the pattern of the table-gradient scatter (F = 2);
+//  - copy:    16-byte vector stream copy, the HBM ceiling.
+// Row numbers come from a counter-based hash of the load index, so no index
+// array is read.
+#include "h4d_device.h"
+
+namespace h4d {
+
+constexpr int kProbeBlock = 256;
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {  // a 32-bit integer finaliser (xorshift-multiply)
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+template <int ROW_BYTES>
+__global__ __launch_bounds__(kProbeBlock) void k_probe_gather(const void* __restrict__ table, uint32_t rows,
+                                                              int64_t n_loads, uint32_t seed, float* __restrict__ sink) {
+    constexpr int kPer = 16;  // independent loads in flight per thread, like the 16 corners
+    const int64_t base = ((int64_t)blockIdx.x * kProbeBlock + threadIdx.x) * kPer;
+    float acc = 0.f;
+    uint32_t r[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) r[k] = mix32((uint32_t)(base + k) ^ seed) % rows;
+    if (ROW_BYTES == 8) {
+        const float2* t = static_cast<const float2*>(table);
+        float2 v[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) v[k] = (base + k < n_loads) ? t[r[k]] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) acc += v[k].x + v[k].y;
+    } else {
+        const float* t = static_cast<const float*>(table);
+        float v[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) v[k] = (base + k < n_loads) ? t[r[k]] : 0.f;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) acc += v[k];
+    }
+    if (acc == 1.2345678f) sink[0] = acc;  // keeps the loads alive; practically never true
+}
+
+__global__ __launch_bounds__(kProbeBlock) void k_probe_scatter(float* __restrict__ table, uint32_t rows,
+                                                               int64_t n_updates, uint32_t seed) {
+    constexpr int kPer = 16;
+    const int64_t base = ((int64_t)blockIdx.x * kProbeBlock + threadIdx.x) * kPer;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (base + k < n_updates) {
+            const uint32_t r = mix32((uint32_t)(base + k) ^ seed) % rows;
+            unsafeAtomicAdd(table + 2 * (size_t)r, 1.0f);
+            unsafeAtomicAdd(table + 2 * (size_t)r + 1, 1.0f);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kProbeBlock) void k_probe_copy(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                            int64_t n4) {
+    for (int64_t i = (int64_t)blockIdx.x * kProbeBlock + threadIdx.x; i < n4; i += (int64_t)gridDim.x * kProbeBlock)
+        dst[i] = src[i];
+}
+
+hipError_t launch_probe_gather(const void* table, uint32_t rows, int row_bytes, int64_t n_loads, uint32_t seed,
+                               float* sink, hipStream_t s) {
+    const int64_t threads = (n_loads + 15) / 16;
+    const dim3 grid((unsigned)((threads + kProbeBlock - 1) / kProbeBlock));
+    if (row_bytes == 8)
+        hipLaunchKernelGGL(k_probe_gather<8>, grid, dim3(kProbeBlock), 0, s, table, rows, n_loads, seed, sink);
+    else
+        hipLaunchKernelGGL(k_probe_gather<4>, grid, dim3(kProbeBlock), 0, s, table, rows, n_loads, seed, sink);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_scatter(float* table, uint32_t rows, int64_t n_updates, uint32_t seed, hipStream_t s) {
+    const int64_t threads = (n_updates + 15) / 16;
+    hipLaunchKernelGGL(k_probe_scatter, dim3((unsigned)((threads + kProbeBlock - 1) / kProbeBlock)),
+                       dim3(kProbeBlock), 0, s, table, rows, n_updates, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+    const int64_t n4 = bytes / 16;
+    int64_t blocks = (n4 + kProbeBlock - 1) / kProbeBlock;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_probe_copy, dim3((unsigned)blocks), dim3(kProbeBlock), 0, s,
+                       static_cast<const float4*>(src), static_cast<float4*>(dst), n4);
+    return hipGetLastError();
+}
+
+}  // namespace h4d

@@ -103,7 +103,7 @@ def test_corrupted_grid_is_rejected_before_launch():
     g.offset[2] += 1
     assert _lib.h4d_grid_rows(g) == -1
     fake = 1 << 20   # never dereferenced: validation fails first
-    st = _lib.load().hash4d_encode(_lib.ctypes.byref(g), 0, fake, fake, 10, fake, None)
+    st = _lib.load().hash4d_encode(_lib.ctypes.byref(g), 0, fake, fake, 10, 0, fake, None)
     assert st == -1 and "inconsistent" in _lib.last_error()
 
 
@@ -112,13 +112,23 @@ def test_entry_points_validate_without_launching():
     g = lib_grid(synth.ENCODER_SMALL)
     gp = _lib.ctypes.byref(g)
     fake = 1 << 20
-    assert lib.hash4d_encode(gp, 0, fake, fake, 0, fake, None) == 0                 # n = 0: no-op
-    assert lib.hash4d_encode(gp, 0, None, fake, 5, fake, None) == -1                # NULL table
-    assert lib.hash4d_encode(gp, 0, fake, fake + 4, 5, fake, None) == -1            # misaligned xyzt
+    assert lib.hash4d_encode(gp, 0, fake, fake, 0, 0, fake, None) == 0                 # n = 0: no-op
+    assert lib.hash4d_encode(gp, 0, None, fake, 5, 0, fake, None) == -1                # NULL table
+    assert lib.hash4d_encode(gp, 0, fake, fake + 4, 5, 0, fake, None) == -1            # misaligned xyzt
     assert "aligned" in _lib.last_error()
-    assert lib.hash4d_encode(gp, 7, fake, fake, 5, fake, None) == -1                # unknown dtype
-    assert lib.hash4d_encode(gp, 0, fake, fake, -1, fake, None) == -1               # negative n
-    assert lib.hash4d_encode(gp, 0, fake, fake, 1 << 31, fake, None) == -1          # n too large
-    assert lib.hash4d_encode_backward(gp, 1, fake, 5, fake, 1.0, fake, None) == -1  # grads must be F32/F64
+    assert lib.hash4d_encode(gp, 7, fake, fake, 5, 0, fake, None) == -1                # unknown dtype
+    assert lib.hash4d_encode(gp, 0, fake, fake, 5, 2, fake, None) == -1                # unknown layout
+    assert lib.hash4d_encode(gp, 0, fake, fake, -1, 0, fake, None) == -1               # negative n
+    assert lib.hash4d_encode(gp, 0, fake, fake, 1 << 31, 0, fake, None) == -1          # n too large
+    assert lib.hash4d_encode_backward(gp, 1, fake, 5, 0, fake, 1.0, fake, None) == -1  # grads must be F32/F64
     assert lib.hash4d_corner_indices(gp, fake, 5, None, None, None) == -1
-    assert lib.hash4d_encode(None, 0, fake, fake, 5, fake, None) == -1
+    assert lib.hash4d_encode(None, 0, fake, fake, 5, 0, fake, None) == -1
+    m = _lib.mlp_shape(32)
+    mp = _lib.ctypes.byref(m)
+    assert lib.deform_mlp_forward(mp, 0, fake, fake, 5, 1, 3, fake, None) == -1            # F must divide in
+    assert lib.deform_mlp_forward(mp, 0, fake, fake, 0, 1, 2, fake, None) == 0             # n = 0
+    bad = _lib.mlp_shape(24)
+    assert lib.deform_mlp_forward(_lib.ctypes.byref(bad), 0, fake, fake, 5, 0, 0, fake, None) == -2
+    assert _lib.deform_mlp_workspace_bytes(m, 0, 200_000) > 0
+    assert _lib.deform_mlp_workspace_bytes(bad, 0, 200_000) == 0
+    assert lib.deform_mlp_backward(mp, 0, fake, fake, 5, 0, 0, fake, 1.0, 1.0, fake, fake, fake, 8, None) == -1

@@ -66,3 +66,29 @@ def needs_gpu():
         ok = False
     if not ok:
         pytest.skip("no GPU")
+
+
+# ------------------------------------------------------- decoder scales ----
+def mlp_forward_scale(flat, f):
+    """Magnitude bound of the decoder forward: every layer on absolute values."""
+    P = O.unpack_params(flat, np.asarray(f).shape[1])
+    s1 = np.abs(f) @ np.abs(P["W1"]).T + np.abs(P["b1"])
+    s2 = s1 @ np.abs(P["W2"]).T + np.abs(P["b2"])
+    s3 = s2 @ np.abs(P["W3"]).T + np.abs(P["b3"])
+    return s3
+
+
+def mlp_backward_scale(flat, f, d_out):
+    """Magnitude bounds of the decoder gradients (d_feat, d_params) on absolute values."""
+    f = np.asarray(f, dtype=np.float64)
+    P = O.unpack_params(flat, f.shape[1])
+    A = {k: np.abs(v) for k, v in P.items()}
+    s1 = np.abs(f) @ A["W1"].T + A["b1"]
+    s2 = s1 @ A["W2"].T + A["b2"]
+    g3 = np.abs(d_out)
+    g2 = g3 @ A["W3"]
+    g1 = g2 @ A["W2"]
+    d_feat = g1 @ A["W1"]
+    d_params = O.pack_params({"W1": g1.T @ np.abs(f), "b1": g1.sum(0), "W2": g2.T @ s1, "b2": g2.sum(0),
+                              "W3": g3.T @ s2, "b3": g3.sum(0)})
+    return d_feat, d_params
