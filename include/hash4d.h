@@ -138,6 +138,18 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
 h4d_status hash4d_corner_indices(const h4d_grid* g, const float* xyzt, int64_t n,
                                  int32_t* rows, float* w, void* stream);
 
+/* ---------------------------------------------------------- smoothness ---- */
+
+/* Smoothness regulariser of Section 4.3 (Eq. 11) and its table gradient, in one
+ * pass: x~ = clamp(x + eps) (FP32 add), d = G(x) - G(x~) over all L F features,
+ *   *loss   += lambda / n * sum_q ||d_q||^2
+ *   d_table += (2 lambda / n) (d w at x's corners - d w~ at x~'s corners)
+ * Nothing is stored: both encodes are recomputed per query and level.  d_table may
+ * be NULL (loss only).  table_dt as hash4d_encode; loss and d_table are FP32
+ * (FP64 for F64).  eps: FP32 [n, 4], 16-byte aligned. */
+h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* table, const float* xyzt,
+                          const float* eps, int64_t n, float lambda, void* loss, void* d_table, void* stream);
+
 /* ----------------------------------------------------- precision form ---- */
 
 /* dst[i] = BF16 (round to nearest even, NaN kept quiet) of the FP32 master src[i],

@@ -64,6 +64,7 @@ SIGNATURES = {
     "hash4d_encode": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _P]),
     "hash4d_encode_backward": (_I32, [_GP, _I32, _P, _I64, _I32, _P, _F32, _P, _P]),
     "hash4d_corner_indices": (_I32, [_GP, _P, _I64, _P, _P, _P]),
+    "smoothness_reg": (_I32, [_GP, _I32, _P, _P, _P, _I64, _F32, _P, _P, _P]),
     "h4d_cast_bf16": (_I32, [_P, _P, _I64, _P]),
     "h4d_count_nonfinite": (_I32, [_P, _I64, _P, _P]),
     "deform_mlp_workspace_bytes": (_SZ, [_MP, _I32, _I64]),
@@ -164,6 +165,12 @@ def hash4d_encode_backward(g: Grid, grad_dt: int, xyzt, n: int, d_feat, grad_sca
 def hash4d_corner_indices(g: Grid, xyzt, n: int, rows, w, stream=None) -> None:
     _check("hash4d_corner_indices", load().hash4d_corner_indices(ctypes.byref(g), ptr(xyzt), n, ptr(rows), ptr(w),
                                                                  stream_handle(stream)))
+
+
+# ------------------------------------------------------------ smoothness ----
+def smoothness_reg(g: Grid, table_dt: int, table, xyzt, eps, n: int, lam: float, loss, d_table, stream=None) -> None:
+    _check("smoothness_reg", load().smoothness_reg(ctypes.byref(g), table_dt, ptr(table), ptr(xyzt), ptr(eps), n, lam,
+                                                   ptr(loss), ptr(d_table), stream_handle(stream)))
 
 
 # ------------------------------------------------------- precision form ----

@@ -248,6 +248,20 @@ h4d_status hash4d_corner_indices(const h4d_grid* g, const float* xyzt, int64_t n
     return hip_status(launch_corner_indices(d, xyzt, (int)n, rows, w, (hipStream_t)stream), "hash4d_corner_indices");
 }
 
+h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* table, const float* xyzt,
+                          const float* eps, int64_t n, float lambda, void* loss, void* d_table, void* stream) {
+    g_last_error.clear();
+    h4d_status st;
+    if ((st = check_grid(g)) || (st = check_dtype(table_dt)) || (st = check_xyzt(xyzt, n))) return st;
+    if (n == 0) return H4D_OK;
+    if (!table || !eps || !loss) return fail(H4D_EINVAL, "table, eps or loss is NULL");
+    if (((uintptr_t)eps) & 15u) return fail(H4D_EINVAL, "eps is not 16-byte aligned");
+    const DevGrid d = to_device(*g);
+    return hip_status(launch_smoothness(d, table_dt, table, xyzt, eps, (int)n, (double)lambda, loss, d_table,
+                                        (hipStream_t)stream),
+                      "smoothness_reg");
+}
+
 h4d_status h4d_cast_bf16(const float* src, uint16_t* dst, int64_t count, void* stream) {
     g_last_error.clear();
     if (count < 0) return fail(H4D_EINVAL, "count=%lld < 0", (long long)count);

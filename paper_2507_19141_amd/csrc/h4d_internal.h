@@ -51,6 +51,10 @@ hipError_t launch_mlp_backward(h4d_dtype dt, int in, int out, const void* params
 hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s);
 hipError_t launch_count_nonfinite(const float* p, int64_t count, int32_t* counter, hipStream_t s);
 
+// ---- smoothness regulariser (smooth.hip) ----
+hipError_t launch_smoothness(const DevGrid& g, h4d_dtype dt, const void* table, const float* xyzt, const float* eps,
+                             int n, double lam, void* loss, void* d_table, hipStream_t s);
+
 // ---- roofline probes (probe.hip) ----
 hipError_t launch_probe_gather(const void* table, uint32_t rows, int row_bytes, int64_t n_loads, uint32_t seed,
                                float* sink, hipStream_t s);

@@ -131,7 +131,6 @@ def test_encode_bf16_table_exact_inputs():
     got = run_encode(lg, _lib.BF16, dev(bits.view(np.int16)), x)
     tb = O.bf16_value(bits)
     scaled_close(got, O.encode(x, tb, og), O.encode(x, np.abs(tb), og), RTOL_F32, "f_h bf16")
-    del torch
 
 
 def test_encode_f64_instantiation():
