@@ -175,8 +175,12 @@ def probes(torch, _lib, E, F, n_loads, reps=5):
     out["gather8_GBps"] = n_loads * 8 / t / 1e9
     t = timed(lambda: _lib.h4d_probe_gather(buf, 2 * E, 4, n_loads, 7, sink))
     out["gather4_GBps"] = n_loads * 4 / t / 1e9
-    t = timed(lambda: _lib.h4d_probe_scatter(buf, E, n_loads, 9))
+    t = timed(lambda: _lib.h4d_probe_scatter(buf, E, n_loads, 9, 0))
     out["scatter8_GBps"] = n_loads * 8 / t / 1e9
+    t = timed(lambda: _lib.h4d_probe_scatter(buf, E, n_loads, 9, 1))
+    out["scatter8_xcd_owned_GBps"] = n_loads * 8 / t / 1e9
+    t = timed(lambda: _lib.h4d_probe_scatter(buf, 1 << 17, n_loads, 9, 0))
+    out["scatter8_1MiB_GBps"] = n_loads * 8 / t / 1e9
     nbytes = 1 << 30
     src = torch.empty(nbytes // 4, device="cuda")
     dst = torch.empty_like(src)

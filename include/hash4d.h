@@ -230,11 +230,15 @@ h4d_status hash4d_deform_backward(const h4d_grid* g, const h4d_mlp* m, h4d_dtype
  *          in flight per thread.  sink: device float, written only in a case that
  *          practically never occurs (it keeps the loads alive).
  * scatter: n_updates updates, each adding 1.0f with a device atomic to both FP32
- *          values of one random 8-byte row of table[rows][2].
+ *          values of one random 8-byte row of table[rows][2].  mode 0: any row;
+ *          mode 1: a row of a 128-byte line whose index is congruent mod 8 to the
+ *          XCC (accelerator complex die) the workgroup runs on, so that each line
+ *          is updated from a single XCC.
  * copy:    bytes (multiple of 16) copied src -> dst with 16-byte vector accesses. */
 h4d_status h4d_probe_gather(const void* table, int64_t rows, int32_t row_bytes, int64_t n_loads, uint32_t seed,
                             float* sink, void* stream);
-h4d_status h4d_probe_scatter(float* table, int64_t rows, int64_t n_updates, uint32_t seed, void* stream);
+h4d_status h4d_probe_scatter(float* table, int64_t rows, int64_t n_updates, uint32_t seed, int32_t mode,
+                             void* stream);
 h4d_status h4d_probe_copy(const void* src, void* dst, int64_t bytes, void* stream);
 
 #ifdef __cplusplus

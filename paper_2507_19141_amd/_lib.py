@@ -74,7 +74,7 @@ SIGNATURES = {
     "hash4d_deform_forward": (_I32, [_GP, _MP, _I32, _P, _P, _P, _I64, _P, _P, _P]),
     "hash4d_deform_backward": (_I32, [_GP, _MP, _I32, _P, _P, _I64, _P, _P, _F32, _F32, _P, _P, _P, _SZ, _P]),
     "h4d_probe_gather": (_I32, [_P, _I64, _I32, _I64, ctypes.c_uint32, _P, _P]),
-    "h4d_probe_scatter": (_I32, [_P, _I64, _I64, ctypes.c_uint32, _P]),
+    "h4d_probe_scatter": (_I32, [_P, _I64, _I64, ctypes.c_uint32, _I32, _P]),
     "h4d_probe_copy": (_I32, [_P, _P, _I64, _P]),
 }
 
@@ -231,8 +231,9 @@ def h4d_probe_gather(table, rows: int, row_bytes: int, n_loads: int, seed: int, 
                                                        stream_handle(stream)))
 
 
-def h4d_probe_scatter(table, rows: int, n_updates: int, seed: int, stream=None) -> None:
-    _check("h4d_probe_scatter", load().h4d_probe_scatter(ptr(table), rows, n_updates, seed, stream_handle(stream)))
+def h4d_probe_scatter(table, rows: int, n_updates: int, seed: int, mode: int = 0, stream=None) -> None:
+    _check("h4d_probe_scatter", load().h4d_probe_scatter(ptr(table), rows, n_updates, seed, mode,
+                                                         stream_handle(stream)))
 
 
 def h4d_probe_copy(src, dst, nbytes: int, stream=None) -> None:

@@ -291,13 +291,15 @@ h4d_status h4d_probe_gather(const void* table, int64_t rows, int32_t row_bytes, 
                       "h4d_probe_gather");
 }
 
-h4d_status h4d_probe_scatter(float* table, int64_t rows, int64_t n_updates, uint32_t seed, void* stream) {
+h4d_status h4d_probe_scatter(float* table, int64_t rows, int64_t n_updates, uint32_t seed, int32_t mode,
+                             void* stream) {
     g_last_error.clear();
     if (rows < 1 || rows > 0xffffffffLL) return fail(H4D_EINVAL, "rows=%lld outside 1..2^32-1", (long long)rows);
     if (n_updates < 0 || n_updates > ((int64_t)1 << 40)) return fail(H4D_EINVAL, "n_updates out of range");
     if (n_updates == 0) return H4D_OK;
     if (!table) return fail(H4D_EINVAL, "table is NULL");
-    return hip_status(launch_probe_scatter(table, (uint32_t)rows, n_updates, seed, (hipStream_t)stream),
+    if (mode != 0 && mode != 1) return fail(H4D_EINVAL, "mode must be 0 or 1");
+    return hip_status(launch_probe_scatter(table, (uint32_t)rows, n_updates, seed, mode, (hipStream_t)stream),
                       "h4d_probe_scatter");
 }
 

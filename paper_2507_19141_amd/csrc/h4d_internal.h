@@ -58,7 +58,8 @@ hipError_t launch_smoothness(const DevGrid& g, h4d_dtype dt, const void* table, 
 // ---- roofline probes (probe.hip) ----
 hipError_t launch_probe_gather(const void* table, uint32_t rows, int row_bytes, int64_t n_loads, uint32_t seed,
                                float* sink, hipStream_t s);
-hipError_t launch_probe_scatter(float* table, uint32_t rows, int64_t n_updates, uint32_t seed, hipStream_t s);
+hipError_t launch_probe_scatter(float* table, uint32_t rows, int64_t n_updates, uint32_t seed, int mode,
+                                hipStream_t s);
 hipError_t launch_probe_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 
 }  // namespace h4d

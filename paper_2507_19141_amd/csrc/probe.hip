@@ -48,14 +48,23 @@ __global__ __launch_bounds__(kProbeBlock) void k_probe_gather(const void* __rest
     if (acc == 1.2345678f) sink[0] = acc;  // keeps the loads alive; practically never true
 }
 
+// mode 0: any random row.  mode 1: a random row of a 128-byte line this XCD owns
+// (line % 8 == the hardware XCC id), so every line is updated from one XCD only.
 __global__ __launch_bounds__(kProbeBlock) void k_probe_scatter(float* __restrict__ table, uint32_t rows,
-                                                               int64_t n_updates, uint32_t seed) {
+                                                               int64_t n_updates, uint32_t seed, int mode) {
     constexpr int kPer = 16;
     const int64_t base = ((int64_t)blockIdx.x * kProbeBlock + threadIdx.x) * kPer;
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u;  // HW_REG_XCC_ID bits [3:0]
+    const uint32_t lines = rows / 16;                                     // 16 rows of 8 bytes per line
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         if (base + k < n_updates) {
-            const uint32_t r = mix32((uint32_t)(base + k) ^ seed) % rows;
+            uint32_t r = mix32((uint32_t)(base + k) ^ seed) % rows;
+            if (mode == 1 && lines >= 8) {
+                uint32_t line = (r / 16) & ~7u;
+                line = line + xcc < lines ? line + xcc : xcc;
+                r = line * 16 + (r & 15);
+            }
             unsafeAtomicAdd(table + 2 * (size_t)r, 1.0f);
             unsafeAtomicAdd(table + 2 * (size_t)r + 1, 1.0f);
         }
@@ -79,10 +88,11 @@ hipError_t launch_probe_gather(const void* table, uint32_t rows, int row_bytes, 
     return hipGetLastError();
 }
 
-hipError_t launch_probe_scatter(float* table, uint32_t rows, int64_t n_updates, uint32_t seed, hipStream_t s) {
+hipError_t launch_probe_scatter(float* table, uint32_t rows, int64_t n_updates, uint32_t seed, int mode,
+                                hipStream_t s) {
     const int64_t threads = (n_updates + 15) / 16;
     hipLaunchKernelGGL(k_probe_scatter, dim3((unsigned)((threads + kProbeBlock - 1) / kProbeBlock)),
-                       dim3(kProbeBlock), 0, s, table, rows, n_updates, seed);
+                       dim3(kProbeBlock), 0, s, table, rows, n_updates, seed, mode);
     return hipGetLastError();
 }
 
