@@ -221,6 +221,79 @@ h4d_status hash4d_deform_backward(const h4d_grid* g, const h4d_mlp* m, h4d_dtype
                                   float loss_scale, float grad_scale, void* d_table, void* d_params,
                                   void* workspace, size_t ws_bytes, void* stream);
 
+/* -------------------------------------------------------- batched form ---- */
+
+#define H4D_MAX_SCENES 16
+#define H4D_MAX_TIMES 8
+#define H4D_MAX_TUNED 64
+
+/* One scene of a batched plan: its own grid, table and decoder, queried at
+ * n_times timestamps per step.  All pointers are device memory owned by the
+ * caller and must stay valid for the plan's lifetime. */
+typedef struct {
+    h4d_grid grid;              /* (host) layout of this scene's table */
+    int64_t n;                  /* dynamic Gaussians */
+    const float* xyz;           /* [n, 4] FP32, 16-byte aligned; the 4th value is ignored */
+    int32_t n_times;            /* 1..8 timestamps per step */
+    float times[H4D_MAX_TIMES]; /* (host) the timestamps, in [0, 1] */
+    void* table;                /* [E, F] in the plan dtype (BF16 bit patterns for BF16) */
+    const float* table_master;  /* BF16 plans: optional FP32 master, rounded into `table` each step */
+    void* params;               /* decoder parameters in the plan dtype */
+    const float* params_master; /* BF16 plans: optional FP32 master, rounded into `params` each step */
+    float* feat;                /* [n_times, L, n, F] FP32, written by the forward */
+    float* delta;               /* [n_times, n, out] FP32, written by the forward */
+    const float* d_delta;       /* [n_times, n, out] FP32 upstream gradient */
+    float* d_table;             /* [E, F] FP32, += grad */
+    float* d_params;            /* [P] FP32, += grad */
+} h4d_scene_desc;
+
+typedef struct h4d_batched_plan h4d_batched_plan;
+
+typedef enum {
+    H4D_PLAN_AUTOTUNE = 1,   /* time candidate schedules at creation and keep the fastest */
+    H4D_PLAN_ZERO_GRADS = 2, /* the backward zeroes d_table / d_params first (a training step) */
+    H4D_PLAN_GRAPH = 4       /* capture forward + backward into one HIP graph for hash4d_batched_run */
+} h4d_plan_flags;
+
+typedef struct {
+    int32_t kernel;          /* 0 = batched encode, 1 = batched scatter */
+    int32_t qpt, lpb, grid;  /* queries per thread, levels per work item, persistent workgroups */
+    float ms;                /* measured milliseconds per launch */
+} h4d_tune_result;
+
+typedef struct {
+    int64_t queries;         /* sum over scenes of n * n_times */
+    int32_t segments;        /* (scene, timestamp) pairs */
+    int32_t encode_qpt, encode_lpb, encode_grid;
+    int32_t scatter_qpt, scatter_lpb, scatter_grid;
+    int32_t graph;           /* 1 if a HIP graph was captured */
+    int32_t n_tuned;
+    h4d_tune_result tuned[H4D_MAX_TUNED];
+} h4d_batched_info;
+
+/* Build a plan for n_scenes (1..16) scenes sharing F and the decoder shape m, in
+ * dt F32 or BF16.  The plan owns device memory of its own (work lists, per-segment
+ * feature gradients, decoder partials; freed by destroy).  With AUTOTUNE the
+ * candidate schedules (queries per thread x levels per item x grid size) of the
+ * encode and scatter kernels are timed on `stream` with the scenes' own data: the
+ * encode candidates write `feat`, the scatter candidates add zero.  With GRAPH the
+ * whole step (BF16 rounding of the masters, encode, decode, decoder backward,
+ * scatter, and zeroing with ZERO_GRADS) is captured into one HIP graph.
+ * Backward scaling: d_delta is multiplied by loss_scale inside the kernels and the
+ * gradients by 1/loss_scale (the BF16 form's loss scaling). */
+h4d_status hash4d_batched_plan_create(h4d_batched_plan** plan, const h4d_scene_desc* scenes, int32_t n_scenes,
+                                      const h4d_mlp* m, h4d_dtype dt, float loss_scale, int32_t flags,
+                                      void* stream);
+/* Forward of every (scene, timestamp): encode then decode (feat, delta). */
+h4d_status hash4d_batched_forward(h4d_batched_plan* plan, void* stream);
+/* Backward of every (scene, timestamp): decoder backward then table scatter. */
+h4d_status hash4d_batched_backward(h4d_batched_plan* plan, void* stream);
+/* One whole step: the captured graph if the plan has one, else forward + backward. */
+h4d_status hash4d_batched_run(h4d_batched_plan* plan, void* stream);
+/* The chosen schedule and the autotuner's measurements. */
+h4d_status hash4d_batched_plan_info(const h4d_batched_plan* plan, h4d_batched_info* info);
+void hash4d_batched_plan_destroy(h4d_batched_plan* plan);
+
 /* ---------------------------------------------------- roofline probes ---- */
 
 /* Measurement kernels for the ceilings the encoder is compared against (not part

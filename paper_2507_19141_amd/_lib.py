@@ -49,6 +49,31 @@ class Mlp(ctypes.Structure):
     _fields_ = [("in_", ctypes.c_int32), ("hidden", ctypes.c_int32), ("out", ctypes.c_int32)]
 
 
+MAX_SCENES, MAX_TIMES, MAX_TUNED = 16, 8, 64
+PLAN_AUTOTUNE, PLAN_ZERO_GRADS, PLAN_GRAPH = 1, 2, 4
+
+
+class SceneDesc(ctypes.Structure):
+    """Mirror of h4d_scene_desc."""
+    _fields_ = [("grid", Grid), ("n", ctypes.c_int64), ("xyz", ctypes.c_void_p), ("n_times", ctypes.c_int32),
+                ("times", ctypes.c_float * MAX_TIMES), ("table", ctypes.c_void_p),
+                ("table_master", ctypes.c_void_p), ("params", ctypes.c_void_p),
+                ("params_master", ctypes.c_void_p), ("feat", ctypes.c_void_p), ("delta", ctypes.c_void_p),
+                ("d_delta", ctypes.c_void_p), ("d_table", ctypes.c_void_p), ("d_params", ctypes.c_void_p)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("qpt", ctypes.c_int32), ("lpb", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
+class BatchedInfo(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_int64), ("segments", ctypes.c_int32), ("encode_qpt", ctypes.c_int32),
+                ("encode_lpb", ctypes.c_int32), ("encode_grid", ctypes.c_int32), ("scatter_qpt", ctypes.c_int32),
+                ("scatter_lpb", ctypes.c_int32), ("scatter_grid", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("n_tuned", ctypes.c_int32), ("tuned", TuneResult * MAX_TUNED)]
+
+
 _P = ctypes.c_void_p
 _I32, _I64, _F32, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
 _GP = ctypes.POINTER(Grid)
@@ -73,6 +98,13 @@ SIGNATURES = {
     "hash4d_deform_workspace_bytes": (_SZ, [_GP, _MP, _I32, _I64]),
     "hash4d_deform_forward": (_I32, [_GP, _MP, _I32, _P, _P, _P, _I64, _P, _P, _P]),
     "hash4d_deform_backward": (_I32, [_GP, _MP, _I32, _P, _P, _I64, _P, _P, _F32, _F32, _P, _P, _P, _SZ, _P]),
+    "hash4d_batched_plan_create": (_I32, [ctypes.POINTER(_P), ctypes.POINTER(SceneDesc), _I32, _MP, _I32, _F32,
+                                          _I32, _P]),
+    "hash4d_batched_forward": (_I32, [_P, _P]),
+    "hash4d_batched_backward": (_I32, [_P, _P]),
+    "hash4d_batched_run": (_I32, [_P, _P]),
+    "hash4d_batched_plan_info": (_I32, [_P, ctypes.POINTER(BatchedInfo)]),
+    "hash4d_batched_plan_destroy": (None, [_P]),
     "h4d_probe_gather": (_I32, [_P, _I64, _I32, _I64, ctypes.c_uint32, _P, _P]),
     "h4d_probe_scatter": (_I32, [_P, _I64, _I64, ctypes.c_uint32, _I32, _P]),
     "h4d_probe_copy": (_I32, [_P, _P, _I64, _P]),
@@ -223,6 +255,60 @@ def hash4d_deform_backward(g: Grid, m: Mlp, dt: int, params, xyzt, n: int, feat,
            load().hash4d_deform_backward(ctypes.byref(g), ctypes.byref(m), dt, ptr(params), ptr(xyzt), n, ptr(feat),
                                          ptr(d_delta), loss_scale, grad_scale, ptr(d_table), ptr(d_params),
                                          ptr(workspace), ws_bytes, stream_handle(stream)))
+
+
+# ----------------------------------------------------------- batched form ----
+class BatchedPlan:
+    """Owns an h4d_batched_plan handle (and keeps the scene array alive)."""
+
+    def __init__(self, scenes: list, m: Mlp, dt: int, loss_scale: float = 1.0, flags: int = 0, stream=None):
+        arr = (SceneDesc * len(scenes))(*scenes)
+        h = ctypes.c_void_p()
+        _check("hash4d_batched_plan_create",
+               load().hash4d_batched_plan_create(ctypes.byref(h), arr, len(scenes), ctypes.byref(m), dt, loss_scale,
+                                                 flags, stream_handle(stream)))
+        self.handle, self._scenes = h, arr
+
+    def forward(self, stream=None) -> None:
+        _check("hash4d_batched_forward", load().hash4d_batched_forward(self.handle, stream_handle(stream)))
+
+    def backward(self, stream=None) -> None:
+        _check("hash4d_batched_backward", load().hash4d_batched_backward(self.handle, stream_handle(stream)))
+
+    def run(self, stream=None) -> None:
+        _check("hash4d_batched_run", load().hash4d_batched_run(self.handle, stream_handle(stream)))
+
+    def info(self) -> BatchedInfo:
+        info = BatchedInfo()
+        _check("hash4d_batched_plan_info", load().hash4d_batched_plan_info(self.handle, ctypes.byref(info)))
+        return info
+
+    def destroy(self) -> None:
+        if self.handle:
+            load().hash4d_batched_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def scene_desc(grid: Grid, n: int, xyz, times, table, params, feat, delta, d_delta, d_table, d_params,
+               table_master=None, params_master=None) -> SceneDesc:
+    d = SceneDesc()
+    d.grid = grid
+    d.n = n
+    d.xyz = ptr(xyz)
+    d.n_times = len(times)
+    for i, t in enumerate(times):
+        d.times[i] = float(t)
+    d.table, d.params = ptr(table), ptr(params)
+    d.table_master, d.params_master = ptr(table_master), ptr(params_master)
+    d.feat, d.delta, d.d_delta = ptr(feat), ptr(delta), ptr(d_delta)
+    d.d_table, d.d_params = ptr(d_table), ptr(d_params)
+    return d
 
 
 # -------------------------------------------------------- roofline probes ----

@@ -112,6 +112,13 @@ static size_t deform_ws(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, int64
     return a + (size_t)n * g->L * g->F * el;
 }
 
+h4d_status validate_grid(const h4d_grid* g) { return check_grid(g); }
+h4d_status set_error(h4d_status st, const char* msg) {
+    g_last_error = msg;
+    return st;
+}
+void clear_error() { g_last_error.clear(); }
+
 }  // namespace h4d
 
 using namespace h4d;

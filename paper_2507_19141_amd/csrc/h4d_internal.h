@@ -24,6 +24,11 @@ struct DevGrid {
 
 // Host-side conversion of a validated h4d_grid.
 DevGrid to_device(const h4d_grid& g);
+// Full validation of a caller-provided grid (sets the thread's last error).
+h4d_status validate_grid(const h4d_grid* g);
+// The thread's last-error text (api.cpp owns it).
+h4d_status set_error(h4d_status st, const char* msg);
+void clear_error();
 
 // ---- encoder launchers (encode.hip) ----
 // out[l * lstride + q * qstride + f]; level-major grid (blockIdx.y = level).
@@ -32,10 +37,55 @@ hipError_t launch_encode(const DevGrid& g, h4d_dtype table_dt, const void* table
 hipError_t launch_encode_backward(const DevGrid& g, h4d_dtype grad_dt, const float* xyzt, int n,
                                   const void* d_feat, int64_t lstride, int64_t qstride, double scale,
                                   void* d_table, hipStream_t s);
+// XCD-partitioned table scatter; ws: scatter_workspace_bytes() of device memory.
+size_t scatter_workspace_bytes();
+hipError_t launch_encode_backward_xcd(const DevGrid& g, h4d_dtype grad_dt, const float* xyzt, int n,
+                                      const void* d_feat, int64_t lstride, int64_t qstride, double scale,
+                                      void* d_table, void* ws, hipStream_t s);
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w,
                                  hipStream_t s);
 
 // ---- decoder launchers (mlp.hip) ----
+constexpr int kMaxMlpSpans = 16;
+
+// Feature k of query q: feat[(k / F) lstride + q qstride + k % F].
+struct FeatView {
+    int64_t lstride, qstride;
+    int logF;
+    __device__ int64_t at(int q, int k) const {
+        return (int64_t)(k >> logF) * lstride + (int64_t)q * qstride + (k & ((1 << logF) - 1));
+    }
+};
+
+// One scene of a decoder launch.  Its `segs` segments (for instance its timestamps)
+// lie back to back: segment s of feat / d_feat starts feat_seg * s elements in, of
+// delta / d_out out_seg * s elements in; fv addresses features inside a segment.
+// Workgroups [block0, block1) of the persistent grid work on this scene only, so
+// each builds its parameter fragments once.
+struct MlpSpan {
+    const void* params;
+    const void* feat;
+    void* delta;
+    const void* d_out;
+    void* d_feat;
+    void* d_params;
+    int64_t feat_seg, out_seg;
+    FeatView fv;
+    int n, segs, block0, block1;
+};
+
+struct MlpBatch {
+    MlpSpan s[kMaxMlpSpans];
+    int count;
+};
+
+// Persistent-grid size of the decoder kernels for a total of `queries` queries.
+int mlp_blocks_for(h4d_dtype dt, bool backward, int64_t queries);
+// Workspace of the decoder backward for a grid of `blocks` workgroups.
+size_t mlp_partial_bytes(h4d_dtype dt, int in, int out, int blocks);
+hipError_t launch_mlp_forward_batch(h4d_dtype dt, int in, int out, const MlpBatch& b, int blocks, hipStream_t s);
+hipError_t launch_mlp_backward_batch(h4d_dtype dt, int in, int out, const MlpBatch& b, int blocks, double in_scale,
+                                     double feat_scale, double param_scale, void* ws, hipStream_t s);
 // Features / feature gradients are addressed as feat[(k / F) lstride + q qstride + k % F].
 size_t mlp_workspace_bytes(h4d_dtype dt, int in, int out, int n);
 hipError_t launch_mlp_forward(h4d_dtype dt, int in, int out, const void* params, const void* feat, int F,

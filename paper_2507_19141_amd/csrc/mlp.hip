@@ -20,6 +20,8 @@
 // for the layer chain, v_mfma_f32_16x16x16_bf16 for weight gradients, FP32
 // accumulation everywhere), and FP64 (the same 16x16x4 tile contraction done with
 // cross-lane reads, for finite-difference gradient checks only).
+#include <string.h>
+
 #include <type_traits>
 
 #include "h4d_device.h"
@@ -239,14 +241,12 @@ __device__ void fill_frags(typename Pol::FE* lds, int count, const typename Pol:
     }
 }
 
-// Feature k of query q: feat[(k / F) lstride + q qstride + k % F].
-struct FeatView {
-    int64_t lstride, qstride;
-    int logF;
-    __device__ int64_t at(int q, int k) const {
-        return (int64_t)(k >> logF) * lstride + (int64_t)q * qstride + (k & ((1 << logF) - 1));
-    }
-};
+__device__ __forceinline__ int span_of_block(const MlpBatch& b) {
+    int si = 0;
+    for (int i = 1; i < b.count; ++i)
+        if ((int)blockIdx.x >= b.s[i].block0) si = i;
+    return si;
+}
 
 // Per-lane biases in accumulator order.
 template <class Pol>
@@ -326,13 +326,13 @@ __device__ __forceinline__ void load_biases(const typename Pol::S* __restrict__ 
 
 // ---------------------------------------------------------------- forward ----
 template <class Pol, int IN>
-__global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(const typename Pol::S* __restrict__ params, int out,
-                                                           const typename Pol::V* __restrict__ feat, FeatView fvw, int n,
-                                                           typename Pol::V* __restrict__ delta) {
+__global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(MlpBatch batch, int out) {
     using Sh = Shape<Pol, IN>;
     using V = typename Pol::V;
     constexpr bool kLds = !std::is_same<Pol, PolF64>::value;
     extern __shared__ __align__(16) unsigned char smem[];
+    const MlpSpan& sp = batch.s[span_of_block(batch)];
+    const typename Pol::S* __restrict__ params = static_cast<const typename Pol::S*>(sp.params);
     const ParamOff po(IN, out);
     Frags<Pol, IN, kLds> fr{reinterpret_cast<const typename Pol::FE*>(smem), params, out, po};
     if constexpr (kLds) fill_frags<Pol, IN>(reinterpret_cast<typename Pol::FE*>(smem), Sh::FWD_FRAGS, params, out, po);
@@ -340,12 +340,18 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(const typename Pol::S
     V b1[16], b2[16], b3[4];
     load_biases<Pol>(params, po, out, b1, b2, b3);
     const int lane = threadIdx.x & 63, j = lane & 15, kb = lane >> 4;
-    const int ntiles = (n + 15) / 16;
-    for (int tile = blockIdx.x * kWaves + (int)(threadIdx.x >> 6); tile < ntiles; tile += gridDim.x * kWaves) {
-        const int q = tile * 16 + j;
+    const int n = sp.n;
+    const int tps = (n + 15) / 16;
+    const int ntiles = tps * sp.segs;
+    const int stride = (sp.block1 - sp.block0) * kWaves;
+    for (int tile = ((int)blockIdx.x - sp.block0) * kWaves + (int)(threadIdx.x >> 6); tile < ntiles; tile += stride) {
+        const int seg = tile / tps;
+        const int q = (tile - seg * tps) * 16 + j;
         const bool valid = q < n;
+        const V* __restrict__ feat = static_cast<const V*>(sp.feat) + (int64_t)seg * sp.feat_seg;
+        V* __restrict__ delta = static_cast<V*>(sp.delta) + (int64_t)seg * sp.out_seg;
         V fv[Sh::NI];
-        load_features<Pol, IN>(feat, fvw, q, valid, fv);
+        load_features<Pol, IN>(feat, sp.fv, q, valid, fv);
         V h1[16], h2[16];
         trunk_forward<Pol, IN>(fr, fv, b1, b2, h1, h2);
         typename Pol::Acc a3 = Pol::zero();
@@ -383,16 +389,17 @@ __device__ __forceinline__ void wgrad(typename Pol::Acc& acc, const typename Pol
 }
 
 template <class Pol, int IN>
-__global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(
-    const typename Pol::S* __restrict__ params, int out, const typename Pol::V* __restrict__ feat, FeatView fvw, int n,
-    const typename Pol::V* __restrict__ d_out, typename Pol::V in_scale, typename Pol::V feat_scale,
-    typename Pol::V* __restrict__ d_feat, FeatView dfw, typename Pol::G* __restrict__ partial) {
+__global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int out, typename Pol::V in_scale,
+                                                            typename Pol::V feat_scale,
+                                                            typename Pol::G* __restrict__ partial) {
     using Sh = Shape<Pol, IN>;
     using V = typename Pol::V;
     using G = typename Pol::G;
     using Acc = typename Pol::Acc;
     constexpr bool kLds = !std::is_same<Pol, PolF64>::value;
     extern __shared__ __align__(16) unsigned char smem[];
+    const MlpSpan& sp = batch.s[span_of_block(batch)];
+    const typename Pol::S* __restrict__ params = static_cast<const typename Pol::S*>(sp.params);
     const ParamOff po(IN, out);
     // LDS: [fragment tables (FP32/BF16 only)][block gradient accumulator (FP32/BF16 only)][transpose buffers]
     typename Pol::FE* frag_lds = reinterpret_cast<typename Pol::FE*>(smem);
@@ -426,12 +433,19 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(
 #pragma unroll
     for (int idx = 0; idx < Sh::NO; ++idx) sb3[idx] = V(0);
 
-    const int ntiles = (n + 15) / 16;
-    for (int tile = blockIdx.x * kWaves + (int)(threadIdx.x >> 6); tile < ntiles; tile += gridDim.x * kWaves) {
-        const int q = tile * 16 + j;
+    const int n = sp.n;
+    const int tps = (n + 15) / 16;
+    const int ntiles = tps * sp.segs;
+    const int stride = (sp.block1 - sp.block0) * kWaves;
+    for (int tile = ((int)blockIdx.x - sp.block0) * kWaves + (int)(threadIdx.x >> 6); tile < ntiles; tile += stride) {
+        const int seg = tile / tps;
+        const int q = (tile - seg * tps) * 16 + j;
         const bool valid = q < n;
+        const V* __restrict__ feat = static_cast<const V*>(sp.feat) + (int64_t)seg * sp.feat_seg;
+        V* __restrict__ d_feat = static_cast<V*>(sp.d_feat) + (int64_t)seg * sp.feat_seg;
+        const V* __restrict__ d_out = static_cast<const V*>(sp.d_out) + (int64_t)seg * sp.out_seg;
         V fv[Sh::NI];
-        load_features<Pol, IN>(feat, fvw, q, valid, fv);
+        load_features<Pol, IN>(feat, sp.fv, q, valid, fv);
         V h1[16], h2[16];
         trunk_forward<Pol, IN>(fr, fv, b1, b2, h1, h2);
         // upstream gradient of the fused heads, scaled on load
@@ -495,7 +509,7 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int f = 16 * mf + 4 * kb + r;
-                    if (f < IN) d_feat[dfw.at(q, f)] = (V)Pol::get(af[mf], r) * feat_scale;
+                    if (f < IN) d_feat[sp.fv.at(q, f)] = (V)Pol::get(af[mf], r) * feat_scale;
                 }
         }
         // Weight gradients: stage G^T and H^T rows through this wavefront's LDS buffer.
@@ -607,15 +621,17 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(
 constexpr int kRedParams = 32, kRedGroups = 8;
 
 template <typename G>
-__global__ __launch_bounds__(kRedParams * kRedGroups) void k_mlp_reduce(const G* __restrict__ partial, int rows,
-                                                                        int P, G scale, G* __restrict__ d_params) {
+__global__ __launch_bounds__(kRedParams * kRedGroups) void k_mlp_reduce(MlpBatch batch, const G* __restrict__ partial,
+                                                                        int rows_per_block, int P, G scale) {
     __shared__ G part[kRedGroups][kRedParams];
+    const MlpSpan& sp = batch.s[blockIdx.y];
+    const int r0 = sp.block0 * rows_per_block, r1 = sp.block1 * rows_per_block;
     const int pl = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
     const int p = blockIdx.x * kRedParams + pl;
     G s = G(0);
     if (p < P) {
 #pragma unroll 8
-        for (int r = grp; r < rows; r += kRedGroups) s += partial[(size_t)r * P + p];
+        for (int r = r0 + grp; r < r1; r += kRedGroups) s += partial[(size_t)r * P + p];
     }
     part[grp][pl] = s;
     __syncthreads();
@@ -623,7 +639,7 @@ __global__ __launch_bounds__(kRedParams * kRedGroups) void k_mlp_reduce(const G*
         G t = G(0);
 #pragma unroll
         for (int g = 0; g < kRedGroups; ++g) t += part[g][pl];
-        d_params[p] += scale * t;
+        static_cast<G*>(sp.d_params)[p] += scale * t;
     }
 }
 
@@ -659,97 +675,128 @@ static size_t lds_backward(int out) {
 }
 
 size_t mlp_workspace_bytes(h4d_dtype dt, int in, int out, int n) {
-    const ParamOff po(in, out);
-    const int rows = dt == H4D_F64 ? mlp_blocks(n, kMlpF64MaxBlocks) * kWaves : mlp_blocks(n, kMlpBwdMaxBlocks);
-    return (size_t)rows * po.P * (dt == H4D_F64 ? sizeof(double) : sizeof(float));
+    return mlp_partial_bytes(dt, in, out, mlp_blocks_for(dt, true, n));
 }
 
 template <class Pol, int IN>
-static hipError_t forward_t(const void* params, int out, const void* feat, const FeatView& fvw, int n, void* delta,
-                            hipStream_t s) {
+static hipError_t forward_t(const MlpBatch& b, int blocks, int out, hipStream_t s) {
     const size_t lds = lds_forward<Pol, IN>();
     auto kern = k_mlp_forward<Pol, IN>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    constexpr bool f64 = std::is_same<Pol, PolF64>::value;
-    hipLaunchKernelGGL(kern, dim3(mlp_blocks(n, f64 ? kMlpF64MaxBlocks : kMlpFwdMaxBlocks)), dim3(kMlpBlock), lds, s,
-                       static_cast<const typename Pol::S*>(params), out, static_cast<const typename Pol::V*>(feat), fvw,
-                       n, static_cast<typename Pol::V*>(delta));
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kMlpBlock), lds, s, b, out);
     return hipGetLastError();
 }
 
 template <class Pol, int IN>
-static hipError_t backward_t(const void* params, int out, const void* feat, const FeatView& fvw, int n,
-                             const void* d_out, double in_scale, double feat_scale, double param_scale, void* d_feat,
-                             const FeatView& dfw, void* d_params, void* ws, hipStream_t s) {
+static hipError_t backward_t(const MlpBatch& b, int blocks, int out, double in_scale, double feat_scale,
+                             double param_scale, void* ws, hipStream_t s) {
     const size_t lds = lds_backward<Pol, IN>(out);
     auto kern = k_mlp_backward<Pol, IN>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     using V = typename Pol::V;
     using G = typename Pol::G;
-    const int blocks = mlp_blocks(n, std::is_same<Pol, PolF64>::value ? kMlpF64MaxBlocks : kMlpBwdMaxBlocks);
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kMlpBlock), lds, s, static_cast<const typename Pol::S*>(params), out,
-                       static_cast<const V*>(feat), fvw, n, static_cast<const V*>(d_out), (V)in_scale, (V)feat_scale,
-                       static_cast<V*>(d_feat), dfw, static_cast<G*>(ws));
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kMlpBlock), lds, s, b, out, (V)in_scale, (V)feat_scale,
+                       static_cast<G*>(ws));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const ParamOff po(IN, out);
-    const int rows = blocks * (std::is_same<Pol, PolF64>::value ? kWaves : 1);
-    hipLaunchKernelGGL(k_mlp_reduce<G>, dim3((po.P + kRedParams - 1) / kRedParams), dim3(kRedParams * kRedGroups), 0,
-                       s, static_cast<const G*>(ws), rows, po.P, (G)param_scale, static_cast<G*>(d_params));
+    const int rows_per_block = std::is_same<Pol, PolF64>::value ? kWaves : 1;
+    hipLaunchKernelGGL(k_mlp_reduce<G>, dim3((po.P + kRedParams - 1) / kRedParams, b.count),
+                       dim3(kRedParams * kRedGroups), 0, s, b, static_cast<const G*>(ws), rows_per_block, po.P,
+                       (G)param_scale);
     return hipGetLastError();
+}
+
+template <class Pol>
+static hipError_t forward_p(int in, const MlpBatch& b, int blocks, int out, hipStream_t s) {
+    switch (in) {
+        case 8: return forward_t<Pol, 8>(b, blocks, out, s);
+        case 16: return forward_t<Pol, 16>(b, blocks, out, s);
+        case 32: return forward_t<Pol, 32>(b, blocks, out, s);
+        case 64: return forward_t<Pol, 64>(b, blocks, out, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class Pol>
+static hipError_t backward_p(int in, const MlpBatch& b, int blocks, int out, double in_scale, double feat_scale,
+                             double param_scale, void* ws, hipStream_t s) {
+    switch (in) {
+        case 8: return backward_t<Pol, 8>(b, blocks, out, in_scale, feat_scale, param_scale, ws, s);
+        case 16: return backward_t<Pol, 16>(b, blocks, out, in_scale, feat_scale, param_scale, ws, s);
+        case 32: return backward_t<Pol, 32>(b, blocks, out, in_scale, feat_scale, param_scale, ws, s);
+        case 64: return backward_t<Pol, 64>(b, blocks, out, in_scale, feat_scale, param_scale, ws, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 static int log2i(int F) { return F == 1 ? 0 : F == 2 ? 1 : F == 4 ? 2 : 3; }
 
-template <class Pol>
-static hipError_t forward_p(int in, const void* params, int out, const void* feat, const FeatView& fvw, int n,
-                            void* delta, hipStream_t s) {
-    switch (in) {
-        case 8: return forward_t<Pol, 8>(params, out, feat, fvw, n, delta, s);
-        case 16: return forward_t<Pol, 16>(params, out, feat, fvw, n, delta, s);
-        case 32: return forward_t<Pol, 32>(params, out, feat, fvw, n, delta, s);
-        case 64: return forward_t<Pol, 64>(params, out, feat, fvw, n, delta, s);
-    }
-    return hipErrorInvalidValue;
+int mlp_blocks_for(h4d_dtype dt, bool backward, int64_t queries) {
+    const int cap = dt == H4D_F64 ? kMlpF64MaxBlocks : backward ? kMlpBwdMaxBlocks : kMlpFwdMaxBlocks;
+    return mlp_blocks((int)(queries < 2147483647 ? queries : 2147483647), cap);
 }
 
-template <class Pol>
-static hipError_t backward_p(int in, const void* params, int out, const void* feat, const FeatView& fvw, int n,
-                             const void* d_out, double in_scale, double feat_scale, double param_scale, void* d_feat,
-                             const FeatView& dfw, void* d_params, void* ws, hipStream_t s) {
-    switch (in) {
-        case 8: return backward_t<Pol, 8>(params, out, feat, fvw, n, d_out, in_scale, feat_scale, param_scale, d_feat, dfw, d_params, ws, s);
-        case 16: return backward_t<Pol, 16>(params, out, feat, fvw, n, d_out, in_scale, feat_scale, param_scale, d_feat, dfw, d_params, ws, s);
-        case 32: return backward_t<Pol, 32>(params, out, feat, fvw, n, d_out, in_scale, feat_scale, param_scale, d_feat, dfw, d_params, ws, s);
-        case 64: return backward_t<Pol, 64>(params, out, feat, fvw, n, d_out, in_scale, feat_scale, param_scale, d_feat, dfw, d_params, ws, s);
-    }
-    return hipErrorInvalidValue;
+size_t mlp_partial_bytes(h4d_dtype dt, int in, int out, int blocks) {
+    const ParamOff po(in, out);
+    return (size_t)blocks * (dt == H4D_F64 ? kWaves : 1) * po.P * (dt == H4D_F64 ? sizeof(double) : sizeof(float));
+}
+
+static MlpBatch single(const void* params, const void* feat, void* delta, const void* d_out, void* d_feat,
+                       void* d_params, int F, int64_t lstride, int64_t qstride, int n, int blocks) {
+    MlpBatch b;
+    memset(&b, 0, sizeof b);
+    b.count = 1;
+    MlpSpan& sp = b.s[0];
+    sp.params = params;
+    sp.feat = feat;
+    sp.delta = delta;
+    sp.d_out = d_out;
+    sp.d_feat = d_feat;
+    sp.d_params = d_params;
+    sp.fv = FeatView{lstride, qstride, log2i(F)};
+    sp.n = n;
+    sp.segs = 1;
+    sp.block0 = 0;
+    sp.block1 = blocks;
+    return b;
 }
 
 hipError_t launch_mlp_forward(h4d_dtype dt, int in, int out, const void* params, const void* feat, int F,
                               int64_t lstride, int64_t qstride, int n, void* delta, hipStream_t s) {
-    const FeatView fvw{lstride, qstride, log2i(F)};
-    switch (dt) {
-        case H4D_F32: return forward_p<PolF32>(in, params, out, feat, fvw, n, delta, s);
-        case H4D_BF16: return forward_p<PolBF16>(in, params, out, feat, fvw, n, delta, s);
-        case H4D_F64: return forward_p<PolF64>(in, params, out, feat, fvw, n, delta, s);
-    }
-    return hipErrorInvalidValue;
+    const int blocks = mlp_blocks_for(dt, false, n);
+    const MlpBatch b = single(params, feat, delta, nullptr, nullptr, nullptr, F, lstride, qstride, n, blocks);
+    return launch_mlp_forward_batch(dt, in, out, b, blocks, s);
 }
 
 hipError_t launch_mlp_backward(h4d_dtype dt, int in, int out, const void* params, const void* feat, int F,
                                int64_t lstride, int64_t qstride, int n, const void* d_out, double in_scale,
                                double feat_scale, double param_scale, void* d_feat, int64_t dlstride, int64_t dqstride,
                                void* d_params, void* ws, hipStream_t s) {
-    const FeatView fvw{lstride, qstride, log2i(F)};
-    const FeatView dfw{dlstride, dqstride, log2i(F)};
+    if (dlstride != lstride || dqstride != qstride) return hipErrorInvalidValue;  // d_feat shares feat's layout
+    const int blocks = mlp_blocks_for(dt, true, n);
+    const MlpBatch b = single(params, feat, nullptr, d_out, d_feat, d_params, F, lstride, qstride, n, blocks);
+    return launch_mlp_backward_batch(dt, in, out, b, blocks, in_scale, feat_scale, param_scale, ws, s);
+}
+
+hipError_t launch_mlp_forward_batch(h4d_dtype dt, int in, int out, const MlpBatch& b, int blocks, hipStream_t s) {
     switch (dt) {
-        case H4D_F32: return backward_p<PolF32>(in, params, out, feat, fvw, n, d_out, in_scale, feat_scale, param_scale, d_feat, dfw, d_params, ws, s);
-        case H4D_BF16: return backward_p<PolBF16>(in, params, out, feat, fvw, n, d_out, in_scale, feat_scale, param_scale, d_feat, dfw, d_params, ws, s);
-        case H4D_F64: return backward_p<PolF64>(in, params, out, feat, fvw, n, d_out, in_scale, feat_scale, param_scale, d_feat, dfw, d_params, ws, s);
+        case H4D_F32: return forward_p<PolF32>(in, b, blocks, out, s);
+        case H4D_BF16: return forward_p<PolBF16>(in, b, blocks, out, s);
+        case H4D_F64: return forward_p<PolF64>(in, b, blocks, out, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_backward_batch(h4d_dtype dt, int in, int out, const MlpBatch& b, int blocks, double in_scale,
+                                     double feat_scale, double param_scale, void* ws, hipStream_t s) {
+    switch (dt) {
+        case H4D_F32: return backward_p<PolF32>(in, b, blocks, out, in_scale, feat_scale, param_scale, ws, s);
+        case H4D_BF16: return backward_p<PolBF16>(in, b, blocks, out, in_scale, feat_scale, param_scale, ws, s);
+        case H4D_F64: return backward_p<PolF64>(in, b, blocks, out, in_scale, feat_scale, param_scale, ws, s);
     }
     return hipErrorInvalidValue;
 }
