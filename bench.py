@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-probes", action="store_true", help="skip the roofline probes")
+    ap.add_argument("--no-batched", action="store_true", help="skip the multi-scene form")
     ap.add_argument("--cpu-sample", type=int, default=40000, help="queries the CPU oracle is timed on")
     return ap.parse_args()
 
@@ -215,6 +216,85 @@ def cpu_baseline(sample: int):
                       f"(f_h, delta) + backward (d_table, d_params) in {dt:.1f} s, 1 thread"}
 
 
+def batched_form(torch, _lib, synth, steps: int, warmup: int):
+    """The multi-scene workload: 8 clustered scenes of 50k..1.2M Gaussians, each at 4
+    timestamps, BF16 tables and decoders rounded from FP32 masters every step, one
+    autotuned plan replayed as a HIP graph.  Also times the same work as per-scene,
+    per-timestamp calls of the plain path, for comparison."""
+    import numpy as np
+    w = synth.PAPER_SCENE
+    m = _lib.mlp_shape(w.n_in)
+    rs = _lib.h4d_grid_schedule(w.L, *w.space)
+    rt = _lib.h4d_grid_schedule(w.L, *w.time)
+    keep, descs = [], []
+    for i, n in enumerate(synth.BATCHED_SCENE_N):
+        rng = np.random.default_rng(i)
+        xyz = synth.clustered_xyz(n, rng)
+        x4 = np.concatenate([xyz, np.zeros((n, 1), np.float32)], axis=1)
+        g = _lib.h4d_grid_init(w.L, w.F, rs, rt, 1 << synth.batched_table_rows_log2(n))
+        table = synth.table_init(g.E, w.F, rng)
+        params = synth.decoder_params(w.n_in, rng)
+        nt = len(synth.BATCHED_TIMES)
+        gd = synth.upstream(n * nt, 10, rng).reshape(nt, n, 10)
+        s = {"g": g, "n": n, "xyz": torch.from_numpy(x4).cuda(), "tm": torch.from_numpy(table).cuda(),
+             "pm": torch.from_numpy(params).cuda(),
+             "t": torch.empty(table.size, dtype=torch.int16, device="cuda"),
+             "p": torch.empty(params.size, dtype=torch.int16, device="cuda"),
+             "feat": torch.empty((nt, w.L, n, w.F), device="cuda"), "delta": torch.empty((nt, n, 10), device="cuda"),
+             "gd": torch.from_numpy(gd).cuda(), "dt": torch.zeros((g.E, w.F), device="cuda"),
+             "dp": torch.zeros(params.size, device="cuda")}
+        keep.append(s)
+        descs.append(_lib.scene_desc(g, n, s["xyz"], synth.BATCHED_TIMES, s["t"], s["p"], s["feat"], s["delta"],
+                                     s["gd"], s["dt"], s["dp"], table_master=s["tm"], params_master=s["pm"]))
+    flags = _lib.PLAN_AUTOTUNE | _lib.PLAN_GRAPH | _lib.PLAN_ZERO_GRADS
+    plan = _lib.BatchedPlan(descs, m, _lib.BF16, 4096.0, flags)
+    info = plan.info()
+    for _ in range(warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    q = info.queries
+    # the same work as plain per-(scene, timestamp) calls
+    ws = {}
+    for s in keep:
+        for k, tv in enumerate(synth.BATCHED_TIMES):
+            s[("x", k)] = s["xyz"].clone().index_fill_(1, torch.tensor([3], device="cuda"), tv)
+    def unbatched():
+        for s in keep:
+            s["dt"].zero_()
+            s["dp"].zero_()
+            _lib.h4d_cast_bf16(s["tm"], s["t"], s["tm"].numel())
+            _lib.h4d_cast_bf16(s["pm"], s["p"], s["pm"].numel())
+            for k, tv in enumerate(synth.BATCHED_TIMES):
+                xt = s[("x", k)]
+                n = s["n"]
+                _lib.hash4d_deform_forward(s["g"], m, _lib.BF16, s["t"], s["p"], xt, n, s["feat"][k], s["delta"][k])
+                wb = _lib.hash4d_deform_workspace_bytes(s["g"], m, _lib.BF16, n)
+                if wb not in ws:
+                    ws[wb] = torch.empty(wb, dtype=torch.uint8, device="cuda")
+                _lib.hash4d_deform_backward(s["g"], m, _lib.BF16, s["p"], xt, n, s["feat"][k], s["gd"][k], 4096.0,
+                                            1 / 4096.0, s["dt"], s["dp"], ws[wb], wb)
+    unbatched()
+    torch.cuda.synchronize()
+    u_steps = max(1, steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(u_steps):
+        unbatched()
+    torch.cuda.synchronize()
+    u_wall = time.perf_counter() - t0
+    plan.destroy()
+    return {"value": q * steps / wall, "ms_per_step": wall * 1e3 / steps, "queries_per_step": q,
+            "scenes": list(synth.BATCHED_SCENE_N), "timestamps": len(synth.BATCHED_TIMES), "dtype": "bf16",
+            "schedule": {"encode_qpt_lpb_grid": [info.encode_qpt, info.encode_lpb, info.encode_grid],
+                         "scatter_tiles": info.scatter_tiles},
+            "graph": bool(info.graph), "unbatched_value": q * u_steps / u_wall,
+            "unbatched_ms_per_step": u_wall * 1e3 / u_steps}
+
+
 def traffic_record(dominant: str):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken
     for the current kernel sources; None otherwise."""
@@ -271,6 +351,9 @@ def main():
                                 "kernels_ms": per_b, "loss_scale": bf.loss_scale}}
     del bf
     torch.cuda.empty_cache()
+    if not args.no_batched:
+        result["forms"]["batched"] = batched_form(torch, _lib, synth, max(3, args.steps // 5), 2)
+        torch.cuda.empty_cache()
     if not args.no_probes:
         w = synth.PAPER_SCENE
         E = _lib.h4d_grid_init(w.L, w.F, _lib.h4d_grid_schedule(w.L, *w.space),

@@ -126,7 +126,9 @@ h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* tabl
  * over every query, level and corner.  Corners and weights are recomputed from
  * xyzt.  grad_dt F32: d_feat and d_table are FP32; F64: both FP64.
  *   d_feat  n L F values in `layout`     d_table [E, F] (+=)
- * Uses device atomics: the summation order, hence the last bits, vary run to run. */
+ * Owner-computes scatter: one workgroup per (level, tile of consecutive table rows)
+ * sums its rows' updates in LDS and adds them to d_table; no device-wide atomics.
+ * LDS atomics make the summation order, hence the last bits, vary run to run. */
 h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
                                   h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
                                   void* stream);
@@ -138,17 +140,29 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
 h4d_status hash4d_corner_indices(const h4d_grid* g, const float* xyzt, int64_t n,
                                  int32_t* rows, float* w, void* stream);
 
+/* Deformation of Eq. 10 from the decoder output: xyz' = xyz + delta[:, 0:3],
+ * rot' = rot + delta[:, 3:7] (the rotation increment added as is), scale' =
+ * scale + delta[:, 7:10], each one FP32 add.  xyz [n, 3], rot [n, 4], scale [n, 3],
+ * delta [n, out] with out >= 10; outputs may alias the inputs.  The gradient of
+ * this step is the identity, so it has no backward entry point. */
+h4d_status hash4d_deform_apply(const float* delta, int64_t n, int32_t out, const float* xyz, const float* rot,
+                               const float* scale, float* xyz_out, float* rot_out, float* scale_out, void* stream);
+
 /* ---------------------------------------------------------- smoothness ---- */
 
-/* Smoothness regulariser of Section 4.3 (Eq. 11) and its table gradient, in one
- * pass: x~ = clamp(x + eps) (FP32 add), d = G(x) - G(x~) over all L F features,
+/* Smoothness regulariser of Section 4.3 (Eq. 11) and its table gradient:
+ * x~ = clamp(x + eps) (FP32 add), d = G(x) - G(x~) over all L F features,
  *   *loss   += lambda / n * sum_q ||d_q||^2
  *   d_table += (2 lambda / n) (d w at x's corners - d w~ at x~'s corners)
- * Nothing is stored: both encodes are recomputed per query and level.  d_table may
- * be NULL (loss only).  table_dt as hash4d_encode; loss and d_table are FP32
- * (FP64 for F64).  eps: FP32 [n, 4], 16-byte aligned. */
+ * Both encodes are recomputed per query and level, nothing is kept between calls.
+ * d_table may be NULL (loss only, no workspace needed).  Otherwise `workspace`
+ * (device, smoothness_workspace_bytes) receives d, and the gradient is added by
+ * the tiled scatter.  table_dt as hash4d_encode; loss and d_table are FP32 (FP64
+ * for F64).  eps: FP32 [n, 4], 16-byte aligned. */
+size_t smoothness_workspace_bytes(const h4d_grid* g, h4d_dtype table_dt, int64_t n);
 h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* table, const float* xyzt,
-                          const float* eps, int64_t n, float lambda, void* loss, void* d_table, void* stream);
+                          const float* eps, int64_t n, float lambda, void* loss, void* d_table, void* workspace,
+                          size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------- precision form ---- */
 
@@ -256,7 +270,7 @@ typedef enum {
 } h4d_plan_flags;
 
 typedef struct {
-    int32_t kernel;          /* 0 = batched encode, 1 = batched scatter */
+    int32_t kernel;          /* 0 = batched encode */
     int32_t qpt, lpb, grid;  /* queries per thread, levels per work item, persistent workgroups */
     float ms;                /* measured milliseconds per launch */
 } h4d_tune_result;
@@ -265,7 +279,7 @@ typedef struct {
     int64_t queries;         /* sum over scenes of n * n_times */
     int32_t segments;        /* (scene, timestamp) pairs */
     int32_t encode_qpt, encode_lpb, encode_grid;
-    int32_t scatter_qpt, scatter_lpb, scatter_grid;
+    int32_t scatter_tiles, scatter_rows_per_tile; /* owner-computes scatter: one workgroup per tile */
     int32_t graph;           /* 1 if a HIP graph was captured */
     int32_t n_tuned;
     h4d_tune_result tuned[H4D_MAX_TUNED];
@@ -275,8 +289,9 @@ typedef struct {
  * dt F32 or BF16.  The plan owns device memory of its own (work lists, per-segment
  * feature gradients, decoder partials; freed by destroy).  With AUTOTUNE the
  * candidate schedules (queries per thread x levels per item x grid size) of the
- * encode and scatter kernels are timed on `stream` with the scenes' own data: the
- * encode candidates write `feat`, the scatter candidates add zero.  With GRAPH the
+ * batched encode kernel are timed on `stream` with the scenes' own data (they
+ * write `feat`).  The scatter runs one workgroup per (scene, level, tile of table
+ * rows), accumulating in LDS over all the scene's timestamps.  With GRAPH the
  * whole step (BF16 rounding of the masters, encode, decode, decoder backward,
  * scatter, and zeroing with ZERO_GRADS) is captured into one HIP graph.
  * Backward scaling: d_delta is multiplied by loss_scale inside the kernels and the

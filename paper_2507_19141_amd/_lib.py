@@ -69,8 +69,8 @@ class TuneResult(ctypes.Structure):
 
 class BatchedInfo(ctypes.Structure):
     _fields_ = [("queries", ctypes.c_int64), ("segments", ctypes.c_int32), ("encode_qpt", ctypes.c_int32),
-                ("encode_lpb", ctypes.c_int32), ("encode_grid", ctypes.c_int32), ("scatter_qpt", ctypes.c_int32),
-                ("scatter_lpb", ctypes.c_int32), ("scatter_grid", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("encode_lpb", ctypes.c_int32), ("encode_grid", ctypes.c_int32), ("scatter_tiles", ctypes.c_int32),
+                ("scatter_rows_per_tile", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("n_tuned", ctypes.c_int32), ("tuned", TuneResult * MAX_TUNED)]
 
 
@@ -89,7 +89,9 @@ SIGNATURES = {
     "hash4d_encode": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _P]),
     "hash4d_encode_backward": (_I32, [_GP, _I32, _P, _I64, _I32, _P, _F32, _P, _P]),
     "hash4d_corner_indices": (_I32, [_GP, _P, _I64, _P, _P, _P]),
-    "smoothness_reg": (_I32, [_GP, _I32, _P, _P, _P, _I64, _F32, _P, _P, _P]),
+    "hash4d_deform_apply": (_I32, [_P, _I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "smoothness_workspace_bytes": (_SZ, [_GP, _I32, _I64]),
+    "smoothness_reg": (_I32, [_GP, _I32, _P, _P, _P, _I64, _F32, _P, _P, _P, _SZ, _P]),
     "h4d_cast_bf16": (_I32, [_P, _P, _I64, _P]),
     "h4d_count_nonfinite": (_I32, [_P, _I64, _P, _P]),
     "deform_mlp_workspace_bytes": (_SZ, [_MP, _I32, _I64]),
@@ -199,10 +201,22 @@ def hash4d_corner_indices(g: Grid, xyzt, n: int, rows, w, stream=None) -> None:
                                                                  stream_handle(stream)))
 
 
+def hash4d_deform_apply(delta, n: int, out: int, xyz, rot, scale, xyz_out, rot_out, scale_out, stream=None) -> None:
+    _check("hash4d_deform_apply", load().hash4d_deform_apply(ptr(delta), n, out, ptr(xyz), ptr(rot), ptr(scale),
+                                                             ptr(xyz_out), ptr(rot_out), ptr(scale_out),
+                                                             stream_handle(stream)))
+
+
 # ------------------------------------------------------------ smoothness ----
-def smoothness_reg(g: Grid, table_dt: int, table, xyzt, eps, n: int, lam: float, loss, d_table, stream=None) -> None:
+def smoothness_workspace_bytes(g: Grid, table_dt: int, n: int) -> int:
+    return int(load().smoothness_workspace_bytes(ctypes.byref(g), table_dt, n))
+
+
+def smoothness_reg(g: Grid, table_dt: int, table, xyzt, eps, n: int, lam: float, loss, d_table, workspace=None,
+                   ws_bytes: int = 0, stream=None) -> None:
     _check("smoothness_reg", load().smoothness_reg(ctypes.byref(g), table_dt, ptr(table), ptr(xyzt), ptr(eps), n, lam,
-                                                   ptr(loss), ptr(d_table), stream_handle(stream)))
+                                                   ptr(loss), ptr(d_table), ptr(workspace), ws_bytes,
+                                                   stream_handle(stream)))
 
 
 # ------------------------------------------------------- precision form ----

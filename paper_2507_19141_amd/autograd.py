@@ -76,11 +76,13 @@ class SmoothnessReg(torch.autograd.Function):
         g = field.grid
         n = xyzt.shape[0]
         loss = torch.zeros(1, dtype=field.torch_dtype, device=xyzt.device)
-        d_table = None
+        d_table, ws, wb = None, None, 0
         if table.requires_grad:
             d_table = torch.zeros(tuple(table.shape), dtype=field.torch_dtype, device=xyzt.device)
+            wb = _lib.smoothness_workspace_bytes(g, field.dtype, n)
+            ws = torch.empty(max(wb, 1), dtype=torch.uint8, device=xyzt.device)
         _lib.smoothness_reg(g, field.dtype, field.lowered(table), xyzt.detach().contiguous(),
-                            eps.detach().contiguous(), n, lam, loss, d_table)
+                            eps.detach().contiguous(), n, lam, loss, d_table, ws, wb)
         ctx.save_for_backward(d_table if d_table is not None else loss)
         ctx.has_grad = d_table is not None
         return loss[0]

@@ -67,6 +67,11 @@ static h4d_status check_grid(const h4d_grid* g) {
     return H4D_OK;
 }
 
+// Rows of each level of a validated grid.
+static void rows_of(const h4d_grid& g, int64_t* rows) {
+    for (int l = 0; l < g.L; ++l) rows[l] = g.offset[l + 1] - g.offset[l];
+}
+
 DevGrid to_device(const h4d_grid& g) {
     DevGrid d;
     memset(&d, 0, sizeof d);
@@ -238,8 +243,10 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
     if (n == 0) return H4D_OK;
     if (!d_feat || !d_table) return fail(H4D_EINVAL, "d_feat or d_table is NULL");
     const DevGrid d = to_device(*g);
-    return hip_status(launch_encode_backward(d, grad_dt, xyzt, (int)n, d_feat, ls, qs, (double)grad_scale, d_table,
-                                             (hipStream_t)stream),
+    int64_t rows[H4D_MAX_LEVELS];
+    rows_of(*g, rows);
+    return hip_status(launch_scatter_tiled(d, rows, grad_dt, xyzt, nullptr, (int)n, d_feat, ls, qs,
+                                           (double)grad_scale, d_table, (hipStream_t)stream),
                       "hash4d_encode_backward");
 }
 
@@ -255,18 +262,38 @@ h4d_status hash4d_corner_indices(const h4d_grid* g, const float* xyzt, int64_t n
     return hip_status(launch_corner_indices(d, xyzt, (int)n, rows, w, (hipStream_t)stream), "hash4d_corner_indices");
 }
 
+size_t smoothness_workspace_bytes(const h4d_grid* g, h4d_dtype table_dt, int64_t n) {
+    if (check_grid(g) != H4D_OK || check_dtype(table_dt) != H4D_OK || n < 0 || n > kMaxN) return 0;
+    return (size_t)n * g->L * g->F * (table_dt == H4D_F64 ? sizeof(double) : sizeof(float));
+}
+
 h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* table, const float* xyzt,
-                          const float* eps, int64_t n, float lambda, void* loss, void* d_table, void* stream) {
+                          const float* eps, int64_t n, float lambda, void* loss, void* d_table, void* workspace,
+                          size_t ws_bytes, void* stream) {
     g_last_error.clear();
     h4d_status st;
     if ((st = check_grid(g)) || (st = check_dtype(table_dt)) || (st = check_xyzt(xyzt, n))) return st;
     if (n == 0) return H4D_OK;
     if (!table || !eps || !loss) return fail(H4D_EINVAL, "table, eps or loss is NULL");
     if (((uintptr_t)eps) & 15u) return fail(H4D_EINVAL, "eps is not 16-byte aligned");
+    if (n * (int64_t)g->L * g->F > kMaxN) return fail(H4D_EINVAL, "n L F exceeds 2^31-1 features");
+    const size_t need = (size_t)n * g->L * g->F * (table_dt == H4D_F64 ? sizeof(double) : sizeof(float));
+    if (d_table && (!workspace || ws_bytes < need))
+        return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
     const DevGrid d = to_device(*g);
-    return hip_status(launch_smoothness(d, table_dt, table, xyzt, eps, (int)n, (double)lambda, loss, d_table,
-                                        (hipStream_t)stream),
-                      "smoothness_reg");
+    const hipStream_t s = (hipStream_t)stream;
+    // pass 1: loss and the feature difference d = G(x) - G(x + eps), level-major [L, n, F]
+    if ((st = hip_status(launch_smoothness(d, table_dt, table, xyzt, eps, (int)n, (double)lambda, loss,
+                                           d_table ? workspace : nullptr, s),
+                         "smoothness_reg/diff")))
+        return st;
+    if (!d_table) return H4D_OK;
+    // pass 2: d_table += (2 lambda / n) (d at x's corners - d at x~'s corners)
+    int64_t rows[H4D_MAX_LEVELS];
+    rows_of(*g, rows);
+    return hip_status(launch_scatter_tiled(d, rows, table_dt == H4D_F64 ? H4D_F64 : H4D_F32, xyzt, eps, (int)n,
+                                           workspace, n * g->F, g->F, 2.0 * (double)lambda / (double)n, d_table, s),
+                      "smoothness_reg/scatter");
 }
 
 h4d_status h4d_cast_bf16(const float* src, uint16_t* dst, int64_t count, void* stream) {
@@ -376,6 +403,19 @@ h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* param
                       "deform_mlp_backward");
 }
 
+h4d_status hash4d_deform_apply(const float* delta, int64_t n, int32_t out, const float* xyz, const float* rot,
+                               const float* scale, float* xyz_out, float* rot_out, float* scale_out, void* stream) {
+    g_last_error.clear();
+    if (n < 0 || n > kMaxN) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-1", (long long)n);
+    if (out < 10 || out > H4D_MAX_OUT) return fail(H4D_EINVAL, "out=%d: the heads need 10 columns", out);
+    if (n == 0) return H4D_OK;
+    if (!delta || !xyz || !rot || !scale || !xyz_out || !rot_out || !scale_out)
+        return fail(H4D_EINVAL, "NULL data pointer");
+    return hip_status(launch_deform_apply(delta, (int)n, out, xyz, rot, scale, xyz_out, rot_out, scale_out,
+                                          (hipStream_t)stream),
+                      "hash4d_deform_apply");
+}
+
 size_t hash4d_deform_workspace_bytes(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, int64_t n) {
     if (check_grid(g) != H4D_OK || check_mlp(m, dt) != H4D_OK || n < 0 || n > kMaxN) return 0;
     return deform_ws(g, m, dt, n);
@@ -430,8 +470,10 @@ h4d_status hash4d_deform_backward(const h4d_grid* g, const h4d_mlp* m, h4d_dtype
                                              loss_scale, 1.0, grad_scale, d_feat, ls, qs, d_params, ws, s),
                          "hash4d_deform_backward/decode")))
         return st;
-    return hip_status(launch_encode_backward(d, dt == H4D_F64 ? H4D_F64 : H4D_F32, xyzt, (int)n, d_feat, ls, qs,
-                                             grad_scale, d_table, s),
+    int64_t rows[H4D_MAX_LEVELS];
+    rows_of(*g, rows);
+    return hip_status(launch_scatter_tiled(d, rows, dt == H4D_F64 ? H4D_F64 : H4D_F32, xyzt, nullptr, (int)n, d_feat,
+                                           ls, qs, grad_scale, d_table, s),
                       "hash4d_deform_backward/encode");
 }
 

@@ -94,37 +94,40 @@ __global__ __launch_bounds__(kBatchBlock) void k_bencode(const BSeg* __restrict_
     }
 }
 
+// One workgroup per (scene, level, tile of rows): the owner-computes scatter of the
+// plain path, scanning every timestamp segment of its scene.
+struct BTile {
+    int scene, level, seg0, nseg;
+    uint32_t base, cnt;  // table rows [base, base + cnt)
+};
+
 template <int F>
 __global__ __launch_bounds__(kBatchBlock) void k_bscatter(const BSeg* __restrict__ segs, const DevGrid* __restrict__ grids,
-                                                          const BRange* __restrict__ ranges, int nranges, int total,
-                                                          BSchedule sch, float scale) {
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const BRange rg = ranges[find_range(ranges, nranges, item)];
-        const BSeg sg = segs[rg.seg];
-        const DevGrid& g = grids[sg.scene];
-        const int tile = item - rg.first;
-        const int l0 = rg.lg * sch.lpb, l1 = min(l0 + sch.lpb, g.L);
-        for (int u = 0; u < sch.qpt; ++u) {
-            const int q = (tile * sch.qpt + u) * kBatchBlock + (int)threadIdx.x;
-            if (q >= sg.n) break;
+                                                          const BTile* __restrict__ tiles, float scale) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* tile = reinterpret_cast<float*>(smem);
+    const BTile tl = tiles[blockIdx.x];
+    const DevGrid& g = grids[tl.scene];
+    const int l = tl.level;
+    for (uint32_t i = threadIdx.x; i < tl.cnt * F; i += kBatchBlock) tile[i] = 0.f;
+    __syncthreads();
+    for (int sgi = tl.seg0; sgi < tl.seg0 + tl.nseg; ++sgi) {
+        const BSeg sg = segs[sgi];
+        for (int q = threadIdx.x; q < sg.n; q += kBatchBlock) {
+            const float* gp = sg.d_feat + ((int64_t)l * sg.n + q) * F;
+            float gv[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) gv[f] = gp[f] * scale;
             float4 x = sg.xyz[q];
             x.w = sg.t;
-            for (int l = l0; l < l1; ++l) {
-                const float* gp = sg.d_feat + ((int64_t)l * sg.n + q) * F;
-                float gf[F];
-#pragma unroll
-                for (int f = 0; f < F; ++f) gf[f] = gp[f] * scale;
-                const Cell c = level_cell(g, l, x);
-                uint32_t row[16];
-                level_rows(g, l, c, row);
-                float w[16];
-                level_weights<float>(c, w);
-#pragma unroll
-                for (int k = 0; k < 16; ++k)
-#pragma unroll
-                    for (int f = 0; f < F; ++f) atomic_add(sg.d_table + (size_t)row[k] * F + f, w[k] * gf[f]);
-            }
+            tile_contrib<float, F>(g, l, x, gv, tl.base, tl.cnt, tile);
         }
+    }
+    __syncthreads();
+    float* out = segs[tl.seg0].d_table + (size_t)tl.base * F;
+    for (uint32_t i = threadIdx.x; i < tl.cnt * F; i += kBatchBlock) {
+        const float v = tile[i];
+        if (v != 0.f) out[i] += v;
     }
 }
 
@@ -151,12 +154,13 @@ struct h4d_batched_plan {
     DevGrid* grids = nullptr;
     BSeg* segs = nullptr;
     BRange* ranges_enc = nullptr;
-    BRange* ranges_sca = nullptr;
-    int nranges_enc = 0, nranges_sca = 0, total_enc = 0, total_sca = 0;
+    BTile* tiles = nullptr;
+    int ntiles = 0;
+    int nranges_enc = 0, total_enc = 0;
     float* d_feat = nullptr;
     void* ws = nullptr;
     size_t ws_bytes = 0;
-    BSchedule enc{1, 1, 2048}, sca{1, 1, 2048};
+    BSchedule enc{1, 1, 2048};
     MlpBatch fwd{}, bwd{};
     int fwd_blocks = 0, bwd_blocks = 0;
     hipGraph_t graph = nullptr;
@@ -229,12 +233,18 @@ static hipError_t launch_bencode(const h4d_batched_plan& p, const BSchedule& s, 
     return hipGetLastError();
 }
 
-static hipError_t launch_bscatter(const h4d_batched_plan& p, const BSchedule& s, float scale, hipStream_t st) {
-    if (p.total_sca == 0) return hipSuccess;
+static hipError_t launch_bscatter(const h4d_batched_plan& p, float scale, hipStream_t st) {
+    if (p.ntiles == 0) return hipSuccess;
     const int F = p.scenes[0].grid.F;
-    const dim3 grid(std::min(s.grid, p.total_sca)), block(kBatchBlock);
-#define H4D_BSCA(FF) hipLaunchKernelGGL((k_bscatter<FF>), grid, block, 0, st, p.segs, p.grids, p.ranges_sca, \
-                                        p.nranges_sca, p.total_sca, s, scale)
+    const size_t lds = (size_t)kTileBytes;
+    const dim3 grid(p.ntiles), block(kBatchBlock);
+#define H4D_BSCA(FF)                                                                                             \
+    do {                                                                                                         \
+        hipError_t e = hipFuncSetAttribute((const void*)k_bscatter<FF>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                           (int)lds);                                                            \
+        if (e != hipSuccess) return e;                                                                           \
+        hipLaunchKernelGGL((k_bscatter<FF>), grid, block, lds, st, p.segs, p.grids, p.tiles, scale);             \
+    } while (0)
     switch (F) {
         case 1: H4D_BSCA(1); break;
         case 2: H4D_BSCA(2); break;
@@ -344,7 +354,7 @@ static hipError_t plan_backward(h4d_batched_plan& p, hipStream_t s) {
     if ((e = launch_mlp_backward_batch(p.dt, p.mlp.in, p.mlp.out, p.bwd, p.bwd_blocks, S, 1.0, 1.0 / S, p.ws, s)) !=
         hipSuccess)
         return e;
-    return launch_bscatter(p, p.sca, (float)(1.0 / S), s);
+    return launch_bscatter(p, (float)(1.0 / S), s);
 }
 
 }  // namespace h4d
@@ -352,9 +362,9 @@ static hipError_t plan_backward(h4d_batched_plan& p, hipStream_t s) {
 namespace h4d {
 
 // Time every candidate schedule (queries per thread x levels per item x grid) of
-// the encode and scatter kernels on the plan's own data and keep the fastest.  The
-// stream is synchronised before a work list is replaced, so no launch ever reads a
-// freed list.
+// the batched encode kernel on the plan's own data and keep the fastest.  The
+// stream is synchronised before a work list is replaced, so no launch ever reads
+// a freed list.
 static hipError_t autotune(h4d_batched_plan& p, const std::vector<BSeg>& segs, hipStream_t st) {
     const int qpts[] = {1, 2};
     const int lpbs[] = {1, 2, 4};
@@ -362,48 +372,38 @@ static hipError_t autotune(h4d_batched_plan& p, const std::vector<BSeg>& segs, h
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
-    for (int which = 0; which < 2 && e == hipSuccess; ++which) {
-        float best = 1e30f;
-        BSchedule best_s = which == 0 ? p.enc : p.sca;
-        BRange** list = which == 0 ? &p.ranges_enc : &p.ranges_sca;
-        int* nr = which == 0 ? &p.nranges_enc : &p.nranges_sca;
-        int* tot = which == 0 ? &p.total_enc : &p.total_sca;
-        auto install = [&](const BSchedule& c) -> hipError_t {
-            hipError_t e2 = hipStreamSynchronize(st);
-            if (e2 != hipSuccess) return e2;
-            std::vector<BRange> rr = build_ranges(p, segs, c, tot);
-            *nr = (int)rr.size();
-            return upload_ranges(list, rr);
-        };
-        // scatter candidates add zero (scale 0): the same atomics, the gradients untouched
-        auto run = [&](const BSchedule& c) {
-            return which == 0 ? launch_bencode(p, c, st) : launch_bscatter(p, c, 0.f, st);
-        };
-        for (int qpt : qpts)
-            for (int lpb : lpbs)
-                for (int gsz : grids) {
-                    if (e != hipSuccess) continue;
-                    const BSchedule cand{qpt, lpb, gsz};
-                    if ((e = install(cand)) != hipSuccess || (e = run(cand)) != hipSuccess) continue;
-                    hipEventRecord(a, st);
-                    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = run(cand);
-                    hipEventRecord(b, st);
-                    if (e == hipSuccess) e = hipEventSynchronize(b);
-                    float ms = 0.f;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-                    if (e != hipSuccess) continue;
-                    ms /= 3.f;
-                    p.tuned.push_back(h4d_tune_result{which, qpt, lpb, gsz, ms});
-                    if (ms < best) {
-                        best = ms;
-                        best_s = cand;
-                    }
+    float best = 1e30f;
+    BSchedule best_s = p.enc;
+    auto install = [&](const BSchedule& c) -> hipError_t {
+        hipError_t e2 = hipStreamSynchronize(st);
+        if (e2 != hipSuccess) return e2;
+        std::vector<BRange> rr = build_ranges(p, segs, c, &p.total_enc);
+        p.nranges_enc = (int)rr.size();
+        return upload_ranges(&p.ranges_enc, rr);
+    };
+    for (int qpt : qpts)
+        for (int lpb : lpbs)
+            for (int gsz : grids) {
+                if (e != hipSuccess) continue;
+                const BSchedule cand{qpt, lpb, gsz};
+                if ((e = install(cand)) != hipSuccess || (e = launch_bencode(p, cand, st)) != hipSuccess) continue;
+                hipEventRecord(a, st);
+                for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = launch_bencode(p, cand, st);
+                hipEventRecord(b, st);
+                if (e == hipSuccess) e = hipEventSynchronize(b);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+                if (e != hipSuccess) continue;
+                ms /= 3.f;
+                p.tuned.push_back(h4d_tune_result{0, qpt, lpb, gsz, ms});
+                if (ms < best) {
+                    best = ms;
+                    best_s = cand;
                 }
-        if (e == hipSuccess) {
-            e = install(best_s);
-            if (which == 0) p.enc = best_s;
-            else p.sca = best_s;
-        }
+            }
+    if (e == hipSuccess) {
+        e = install(best_s);
+        p.enc = best_s;
     }
     if (a) hipEventDestroy(a);
     if (b) hipEventDestroy(b);
@@ -491,6 +491,25 @@ h4d_status hash4d_batched_plan_create(h4d_batched_plan** out, const h4d_scene_de
         (e = hipMalloc((void**)&p->segs, segs.size() * sizeof(BSeg))) != hipSuccess ||
         (e = hipMemcpy(p->segs, segs.data(), segs.size() * sizeof(BSeg), hipMemcpyHostToDevice)) != hipSuccess)
         return bail(plan_hip(e, "plan tables"));
+    // scatter tiles: (scene, level, rows) with at most kTileBytes of FP32 rows each
+    {
+        std::vector<BTile> tiles;
+        int seg0 = 0;
+        for (int sc = 0; sc < n_scenes; ++sc) {
+            const h4d_scene_desc& d = scenes[sc];
+            const int rpt = kTileBytes / (d.grid.F * (int)sizeof(float));
+            for (int l = 0; l < d.grid.L; ++l) {
+                const int64_t r0 = d.grid.offset[l], r1 = d.grid.offset[l + 1];
+                for (int64_t r = r0; r < r1; r += rpt)
+                    tiles.push_back(BTile{sc, l, seg0, d.n_times, (uint32_t)r, (uint32_t)std::min<int64_t>(rpt, r1 - r)});
+            }
+            seg0 += d.n_times;
+        }
+        p->ntiles = (int)tiles.size();
+        if ((e = hipMalloc((void**)&p->tiles, std::max<size_t>(1, tiles.size()) * sizeof(BTile))) != hipSuccess ||
+            (e = hipMemcpy(p->tiles, tiles.data(), tiles.size() * sizeof(BTile), hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(plan_hip(e, "plan tiles"));
+    }
     // decoder spans
     p->fwd_blocks = mlp_blocks_for(dt, false, queries);
     p->bwd_blocks = std::max(mlp_blocks_for(dt, true, queries), n_scenes);
@@ -509,9 +528,6 @@ h4d_status hash4d_batched_plan_create(h4d_batched_plan** out, const h4d_scene_de
     std::vector<BRange> r = build_ranges(*p, segs, p->enc, &p->total_enc);
     p->nranges_enc = (int)r.size();
     if ((e = upload_ranges(&p->ranges_enc, r)) != hipSuccess) return bail(plan_hip(e, "plan ranges"));
-    r = build_ranges(*p, segs, p->sca, &p->total_sca);
-    p->nranges_sca = (int)r.size();
-    if ((e = upload_ranges(&p->ranges_sca, r)) != hipSuccess) return bail(plan_hip(e, "plan ranges"));
     if (flags & H4D_PLAN_AUTOTUNE) {
         if ((e = autotune(*p, segs, st)) != hipSuccess) return bail(plan_hip(e, "autotune"));
     }
@@ -567,9 +583,8 @@ h4d_status hash4d_batched_plan_info(const h4d_batched_plan* p, h4d_batched_info*
     info->encode_qpt = p->enc.qpt;
     info->encode_lpb = p->enc.lpb;
     info->encode_grid = p->enc.grid;
-    info->scatter_qpt = p->sca.qpt;
-    info->scatter_lpb = p->sca.lpb;
-    info->scatter_grid = p->sca.grid;
+    info->scatter_tiles = p->ntiles;
+    info->scatter_rows_per_tile = kTileBytes / (p->scenes[0].grid.F * (int)sizeof(float));
     info->graph = p->exec != nullptr;
     info->n_tuned = (int32_t)std::min<size_t>(p->tuned.size(), H4D_MAX_TUNED);
     for (int i = 0; i < info->n_tuned; ++i) info->tuned[i] = p->tuned[i];
@@ -583,7 +598,7 @@ void hash4d_batched_plan_destroy(h4d_batched_plan* p) {
     hipFree(p->grids);
     hipFree(p->segs);
     hipFree(p->ranges_enc);
-    hipFree(p->ranges_sca);
+    hipFree(p->tiles);
     hipFree(p->d_feat);
     hipFree(p->ws);
     delete p;

@@ -1,10 +1,12 @@
 // 4D hash encoder forward and backward kernels (DASH Section 4.2, Eqs. 8-9).
 //
-// One thread per (query, level).  The grid is level-major (blockIdx.y = level):
+// Forward: one thread per (query, level).  The grid is level-major (blockIdx.y = level):
 // the hardware dispatches workgroups in linear order, so at any moment the chip
 // works on one or two levels and each XCD's L2 holds mostly that level's slice of
 // the table (4 MiB FP32 / 2 MiB BF16 for a 2^19-row, F = 2 level) instead of the
 // whole table.
+#include <string.h>
+
 #include "h4d_device.h"
 
 namespace h4d {
@@ -44,121 +46,54 @@ __global__ __launch_bounds__(kEncodeBlock) void k_encode(DevGrid g, const TT* __
     }
 }
 
-template <typename G, int F>
-__global__ __launch_bounds__(kEncodeBlock) void k_encode_backward(DevGrid g, const float4* __restrict__ xyzt, int n,
-                                                                  const G* __restrict__ d_feat, int64_t lstride,
-                                                                  int64_t qstride, G scale, G* __restrict__ d_table) {
-    const int l = blockIdx.y;
-    const int q = blockIdx.x * kEncodeBlock + threadIdx.x;
-    if (q >= n) return;
-    const G* gp = d_feat + (int64_t)l * lstride + (int64_t)q * qstride;
-    G gf[F];
+// ------------------------------------------------------ tiled table scatter ----
+// Device-scope FP32 atomics on MI355X complete at a fixed rate of about 2e10 per
+// second whatever the footprint (they are not executed in the XCD-local L2), so
+// the scatter avoids them altogether.  Owner computes: one workgroup per (level,
+// tile of R consecutive table rows of that level) keeps the tile's gradient in LDS,
+// scans every query of the level, adds w_c g for the corners that fall in its tile
+// with LDS atomics, and finally adds the tile to d_table with plain loads and
+// stores (no other workgroup owns those rows).  With pi_1 = 1 the two x-corners of
+// a hashed level share a tile, so a query touches at most 8 tiles per level.
+// PAIR: each query also subtracts the same gradient at the corners of x + eps (the
+// second term of Eq. 11).
+template <typename G, int F, bool PAIR>
+__global__ __launch_bounds__(kEncodeBlock) void k_scatter_tiled(DevGrid g, TileMap tm, const float4* __restrict__ xyzt,
+                                                                const float4* __restrict__ eps, int n,
+                                                                const G* __restrict__ src, int64_t lstride,
+                                                                int64_t qstride, G scale, G* __restrict__ d_table) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    G* tile = reinterpret_cast<G*>(smem);
+    int l = 0;
+    while (l + 1 < g.L && (int)blockIdx.x >= tm.tile_start[l + 1]) ++l;
+    const uint32_t first = (uint32_t)((int)blockIdx.x - tm.tile_start[l]) * (uint32_t)tm.rows_per_tile;
+    const uint32_t base = g.off[l] + first;
+    const uint32_t cnt = min((uint32_t)tm.rows_per_tile, (uint32_t)tm.level_rows[l] - first);
+    for (uint32_t i = threadIdx.x; i < cnt * F; i += kEncodeBlock) tile[i] = G(0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < n; q += kEncodeBlock) {
+        const G* gp = src + (int64_t)l * lstride + (int64_t)q * qstride;
+        G gv[F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) gf[f] = gp[f] * scale;
-    const Cell c = level_cell(g, l, xyzt[q]);
-    uint32_t row[16];
-    level_rows(g, l, c, row);
-    G w[16];
-    level_weights<G>(c, w);
+        for (int f = 0; f < F; ++f) gv[f] = gp[f] * scale;
+        const float4 x = xyzt[q];
+        tile_contrib<G, F>(g, l, x, gv, base, cnt, tile);
+        if constexpr (PAIR) {
+            const float4 e = eps[q];
+            const float4 xp = make_float4(__fadd_rn(x.x, e.x), __fadd_rn(x.y, e.y), __fadd_rn(x.z, e.z),
+                                          __fadd_rn(x.w, e.w));
+            G gm[F];
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-#pragma unroll
-        for (int f = 0; f < F; ++f) atomic_add(d_table + (size_t)row[k] * F + f, w[k] * gf[f]);
-}
-
-// ------------------------------------------------- XCD-partitioned scatter ----
-// The table gradient is split by 128-byte line: line i belongs to slot i % 8.  A
-// workgroup reads the hardware id of the XCC (accelerator complex die) it runs on
-// and applies only the updates that fall in lines of that slot, pulling work items
-// (a group of levels x a tile of queries) from its slot's queue until the queue is
-// exhausted.  Every line is therefore updated from one XCC only, and its atomics
-// can complete in that XCC's L2.  The last workgroup to finish processes any slot
-// whose queue no workgroup touched (an XCC that received no workgroup), so the
-// result never depends on how the dispatcher spreads workgroups over XCCs, and
-// resets the queues for the next call.
-constexpr int kXcdSlots = 8;
-constexpr int kScatterLevelsPerItem = 4;
-struct ScatterCtl {
-    int next[kXcdSlots];
-    int done;
-};
-
-__device__ __forceinline__ uint32_t xcc_slot() {
-    return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (kXcdSlots - 1);  // HW_REG_XCC_ID bits [3:0]
-}
-
-template <typename G, int F>
-__device__ __forceinline__ void scatter_item(const DevGrid& g, const float4* __restrict__ xyzt, int n,
-                                             const G* __restrict__ d_feat, int64_t lstride, int64_t qstride, G scale,
-                                             G* __restrict__ d_table, int item, int ntiles, uint32_t slot) {
-    const int lg = item / ntiles, tile = item - lg * ntiles;
-    const int q = tile * kEncodeBlock + (int)threadIdx.x;
-    if (q >= n) return;
-    const float4 x = xyzt[q];
-    const int l0 = lg * kScatterLevelsPerItem;
-    const int l1 = min(l0 + kScatterLevelsPerItem, g.L);
-    constexpr int kLineShift = (F * (int)sizeof(G) == 8) ? 4 : (F * (int)sizeof(G) == 4) ? 5 : (F * (int)sizeof(G) == 16) ? 3 : (F * (int)sizeof(G) == 32) ? 2 : 1;
-    for (int l = l0; l < l1; ++l) {
-        const G* gp = d_feat + (int64_t)l * lstride + (int64_t)q * qstride;
-        G gf[F];
-#pragma unroll
-        for (int f = 0; f < F; ++f) gf[f] = gp[f] * scale;
-        const Cell c = level_cell(g, l, x);
-        uint32_t row[16];
-        level_rows(g, l, c, row);
-        G w[16];
-        level_weights<G>(c, w);
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (((row[k] >> kLineShift) & (kXcdSlots - 1)) == slot) {
-#pragma unroll
-                for (int f = 0; f < F; ++f) atomic_add(d_table + (size_t)row[k] * F + f, w[k] * gf[f]);
-            }
+            for (int f = 0; f < F; ++f) gm[f] = -gv[f];
+            tile_contrib<G, F>(g, l, xp, gm, base, cnt, tile);
         }
     }
-}
-
-template <typename G, int F>
-__global__ __launch_bounds__(kEncodeBlock) void k_encode_backward_xcd(DevGrid g, const float4* __restrict__ xyzt,
-                                                                      int n, const G* __restrict__ d_feat,
-                                                                      int64_t lstride, int64_t qstride, G scale,
-                                                                      G* __restrict__ d_table, ScatterCtl* ctl) {
-    __shared__ int s_item;
-    const uint32_t slot = xcc_slot();
-    const int ntiles = (n + kEncodeBlock - 1) / kEncodeBlock;
-    const int groups = (g.L + kScatterLevelsPerItem - 1) / kScatterLevelsPerItem;
-    const int total = groups * ntiles;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&ctl->next[slot], 1);
-        __syncthreads();
-        const int item = s_item;
-        __syncthreads();
-        if (item >= total) break;
-        scatter_item<G, F>(g, xyzt, n, d_feat, lstride, qstride, scale, d_table, item, ntiles, slot);
-    }
-    __shared__ int s_last;
-    __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(&ctl->done, 1) == (int)gridDim.x - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    for (int s = 0; s < kXcdSlots; ++s) {
-        const int start = __hip_atomic_load(&ctl->next[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (int item = start; item < total; ++item)
-            scatter_item<G, F>(g, xyzt, n, d_feat, lstride, qstride, scale, d_table, item, ntiles, (uint32_t)s);
+    G* out = d_table + (size_t)base * F;
+    for (uint32_t i = threadIdx.x; i < cnt * F; i += kEncodeBlock) {
+        const G v = tile[i];
+        if (v != G(0)) out[i] += v;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int s = 0; s < kXcdSlots; ++s) ctl->next[s] = 0;
-        ctl->done = 0;
-        __threadfence();
-    }
-}
-
-__global__ void k_scatter_ctl_reset(ScatterCtl* ctl) {
-    if (threadIdx.x < kXcdSlots) ctl->next[threadIdx.x] = 0;
-    if (threadIdx.x == 0) ctl->done = 0;
 }
 
 __global__ __launch_bounds__(kEncodeBlock) void k_corner_indices(DevGrid g, const float4* __restrict__ xyzt, int n,
@@ -210,58 +145,56 @@ hipError_t launch_encode(const DevGrid& g, h4d_dtype dt, const void* table, cons
     return hipErrorInvalidValue;
 }
 
-template <typename G>
-static hipError_t encode_backward_t(const DevGrid& g, const float* xyzt, int n, const void* d_feat, int64_t ls,
-                                    int64_t qs, double scale, void* d_table, hipStream_t s) {
-    const dim3 grid = level_major_grid(n, g.L), block(kEncodeBlock);
-    const float4* x = reinterpret_cast<const float4*>(xyzt);
-    const G* df = static_cast<const G*>(d_feat);
-    G* dt = static_cast<G*>(d_table);
-    const G sc = (G)scale;
-    switch (g.F) {
-        case 1: hipLaunchKernelGGL((k_encode_backward<G, 1>), grid, block, 0, s, g, x, n, df, ls, qs, sc, dt); break;
-        case 2: hipLaunchKernelGGL((k_encode_backward<G, 2>), grid, block, 0, s, g, x, n, df, ls, qs, sc, dt); break;
-        case 4: hipLaunchKernelGGL((k_encode_backward<G, 4>), grid, block, 0, s, g, x, n, df, ls, qs, sc, dt); break;
-        case 8: hipLaunchKernelGGL((k_encode_backward<G, 8>), grid, block, 0, s, g, x, n, df, ls, qs, sc, dt); break;
-        default: return hipErrorInvalidValue;
+// Tiles of at most 128 KiB of LDS; tile_start is the first tile of each level.
+TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes) {
+    TileMap tm;
+    memset(&tm, 0, sizeof tm);
+    tm.rows_per_tile = kTileBytes / (F * gbytes);
+    int t = 0;
+    for (int l = 0; l < g.L; ++l) {
+        tm.tile_start[l] = t;
+        tm.level_rows[l] = (int32_t)level_rows[l];
+        t += (int)((level_rows[l] + tm.rows_per_tile - 1) / tm.rows_per_tile);
     }
+    tm.tile_start[g.L] = t;
+    return tm;
+}
+
+template <typename G, int F, bool PAIR>
+static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt, const float* eps, int n,
+                          const void* src, int64_t ls, int64_t qs, double scale, void* d_table, hipStream_t s) {
+    auto kern = k_scatter_tiled<G, F, PAIR>;
+    const size_t lds = (size_t)tm.rows_per_tile * F * sizeof(G);
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(tm.tile_start[g.L]), dim3(kEncodeBlock), lds, s, g, tm,
+                       reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n,
+                       static_cast<const G*>(src), ls, qs, (G)scale, static_cast<G*>(d_table));
     return hipGetLastError();
 }
 
-hipError_t launch_encode_backward(const DevGrid& g, h4d_dtype grad_dt, const float* xyzt, int n, const void* d_feat,
-                                  int64_t ls, int64_t qs, double scale, void* d_table, hipStream_t s) {
-    if (grad_dt == H4D_F64) return encode_backward_t<double>(g, xyzt, n, d_feat, ls, qs, scale, d_table, s);
-    return encode_backward_t<float>(g, xyzt, n, d_feat, ls, qs, scale, d_table, s);
-}
-
-size_t scatter_workspace_bytes() { return 256; }
-
-template <typename G>
-static hipError_t encode_backward_xcd_t(const DevGrid& g, const float* xyzt, int n, const void* d_feat, int64_t ls,
-                                        int64_t qs, double scale, void* d_table, void* ws, hipStream_t s) {
-    const float4* x = reinterpret_cast<const float4*>(xyzt);
-    const G* df = static_cast<const G*>(d_feat);
-    G* dt = static_cast<G*>(d_table);
-    const G sc = (G)scale;
-    ScatterCtl* ctl = static_cast<ScatterCtl*>(ws);
-    hipLaunchKernelGGL(k_scatter_ctl_reset, dim3(1), dim3(64), 0, s, ctl);
-    // enough workgroups to fill every CU twice; each XCC pulls its own queue
-    const dim3 grid(kXcdSlots * 64), block(kEncodeBlock);
+template <typename G, bool PAIR>
+static hipError_t tiled_g(const DevGrid& g, const int64_t* level_rows, const float* xyzt, const float* eps, int n,
+                          const void* src, int64_t ls, int64_t qs, double scale, void* d_table, hipStream_t s) {
+    const TileMap tm = make_tile_map(g, level_rows, g.F, (int)sizeof(G));
     switch (g.F) {
-        case 1: hipLaunchKernelGGL((k_encode_backward_xcd<G, 1>), grid, block, 0, s, g, x, n, df, ls, qs, sc, dt, ctl); break;
-        case 2: hipLaunchKernelGGL((k_encode_backward_xcd<G, 2>), grid, block, 0, s, g, x, n, df, ls, qs, sc, dt, ctl); break;
-        case 4: hipLaunchKernelGGL((k_encode_backward_xcd<G, 4>), grid, block, 0, s, g, x, n, df, ls, qs, sc, dt, ctl); break;
-        case 8: hipLaunchKernelGGL((k_encode_backward_xcd<G, 8>), grid, block, 0, s, g, x, n, df, ls, qs, sc, dt, ctl); break;
-        default: return hipErrorInvalidValue;
+        case 1: return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, src, ls, qs, scale, d_table, s);
+        case 2: return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, src, ls, qs, scale, d_table, s);
+        case 4: return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, src, ls, qs, scale, d_table, s);
+        case 8: return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, src, ls, qs, scale, d_table, s);
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_encode_backward_xcd(const DevGrid& g, h4d_dtype grad_dt, const float* xyzt, int n,
-                                      const void* d_feat, int64_t ls, int64_t qs, double scale, void* d_table,
-                                      void* ws, hipStream_t s) {
-    if (grad_dt == H4D_F64) return encode_backward_xcd_t<double>(g, xyzt, n, d_feat, ls, qs, scale, d_table, ws, s);
-    return encode_backward_xcd_t<float>(g, xyzt, n, d_feat, ls, qs, scale, d_table, ws, s);
+hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d_dtype grad_dt, const float* xyzt,
+                                const float* eps, int n, const void* src, int64_t ls, int64_t qs, double scale,
+                                void* d_table, hipStream_t s) {
+    if (grad_dt == H4D_F64) {
+        return eps ? tiled_g<double, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, s)
+                   : tiled_g<double, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, s);
+    }
+    return eps ? tiled_g<float, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, s)
+               : tiled_g<float, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, s);
 }
 
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w, hipStream_t s) {

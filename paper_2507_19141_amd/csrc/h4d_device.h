@@ -164,4 +164,27 @@ template <> struct AccOf<double> { using type = double; };
 __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
+// Add w_c gv at the corners of x that fall in table rows [base, base + cnt) to an
+// LDS tile (row r at tile[(r - base) F]).
+template <typename G, int F>
+__device__ __forceinline__ void tile_contrib(const DevGrid& g, int l, float4 x, const G (&gv)[F], uint32_t base,
+                                             uint32_t cnt, G* tile) {
+    const Cell c = level_cell(g, l, x);
+    uint32_t row[16];
+    level_rows(g, l, c, row);
+    const G wx[2] = {G(1) - G(c.fx), G(c.fx)};
+    const G wy[2] = {G(1) - G(c.fy), G(c.fy)};
+    const G wz[2] = {G(1) - G(c.fz), G(c.fz)};
+    const G wt[2] = {G(1) - G(c.ft), G(c.ft)};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t r = row[k] - base;
+        if (r < cnt) {
+            const G w = ((wx[k & 1] * wy[(k >> 1) & 1]) * wz[(k >> 2) & 1]) * wt[k >> 3];
+#pragma unroll
+            for (int f = 0; f < F; ++f) atomicAdd(tile + r * F + f, w * gv[f]);
+        }
+    }
+}
+
 }  // namespace h4d

@@ -34,14 +34,19 @@ void clear_error();
 // out[l * lstride + q * qstride + f]; level-major grid (blockIdx.y = level).
 hipError_t launch_encode(const DevGrid& g, h4d_dtype table_dt, const void* table, const float* xyzt, int n,
                          void* out, int64_t lstride, int64_t qstride, hipStream_t s);
-hipError_t launch_encode_backward(const DevGrid& g, h4d_dtype grad_dt, const float* xyzt, int n,
-                                  const void* d_feat, int64_t lstride, int64_t qstride, double scale,
-                                  void* d_table, hipStream_t s);
-// XCD-partitioned table scatter; ws: scatter_workspace_bytes() of device memory.
-size_t scatter_workspace_bytes();
-hipError_t launch_encode_backward_xcd(const DevGrid& g, h4d_dtype grad_dt, const float* xyzt, int n,
-                                      const void* d_feat, int64_t lstride, int64_t qstride, double scale,
-                                      void* d_table, void* ws, hipStream_t s);
+// Tiled (owner-computes) table scatter: one workgroup per (level, tile of
+// consecutive table rows), accumulating in LDS.  level_rows[l] = rows of level l.
+// eps != NULL: each query also subtracts its gradient at the corners of x + eps.
+constexpr int kTileBytes = 128 * 1024;
+struct TileMap {
+    int32_t rows_per_tile;
+    int32_t tile_start[H4D_MAX_LEVELS + 1];
+    int32_t level_rows[H4D_MAX_LEVELS];
+};
+TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes);
+hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d_dtype grad_dt, const float* xyzt,
+                                const float* eps, int n, const void* src, int64_t lstride, int64_t qstride,
+                                double scale, void* d_table, hipStream_t s);
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w,
                                  hipStream_t s);
 
@@ -100,10 +105,13 @@ hipError_t launch_mlp_backward(h4d_dtype dt, int in, int out, const void* params
 // ---- precision helpers (precision.hip) ----
 hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s);
 hipError_t launch_count_nonfinite(const float* p, int64_t count, int32_t* counter, hipStream_t s);
+hipError_t launch_deform_apply(const float* delta, int n, int out, const float* x, const float* r, const float* s,
+                               float* xo, float* ro, float* so, hipStream_t st);
 
 // ---- smoothness regulariser (smooth.hip) ----
+// Loss (+=) and, if d_out != NULL, the level-major difference G(x) - G(x + eps).
 hipError_t launch_smoothness(const DevGrid& g, h4d_dtype dt, const void* table, const float* xyzt, const float* eps,
-                             int n, double lam, void* loss, void* d_table, hipStream_t s);
+                             int n, double lam, void* loss, void* d_out, hipStream_t s);
 
 // ---- roofline probes (probe.hip) ----
 hipError_t launch_probe_gather(const void* table, uint32_t rows, int row_bytes, int64_t n_loads, uint32_t seed,

@@ -368,23 +368,40 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(MlpBatch batch, int o
 }
 
 // --------------------------------------------------------------- backward ----
-// Weight-gradient tile product over the 16 queries of a tile:
-// acc[i][j] += sum_q tb[ra + i][q] * tb[rb + j][q].
+// Weight-gradient operands over the 16 queries of a tile.  For the 16x16 block
+// whose rows start at row r0 of the transpose buffer, lane (i, kb) holds the
+// values of row r0 + i at the queries it contributes: q = 4c + kb for chunk c
+// (FP32 / FP64, four 16x16x4 products) or q = 4kb + e (BF16, one 16x16x16 product).
 template <class Pol>
-__device__ __forceinline__ void wgrad(typename Pol::Acc& acc, const typename Pol::V* tb, int ra, int rb) {
+struct WOp {
+    typename Pol::V v[4];
+};
+
+template <class Pol>
+__device__ __forceinline__ WOp<Pol> wload(const typename Pol::V* tb, int r0) {
     const int lane = threadIdx.x & 63, i = lane & 15, kb = lane >> 4;
+    WOp<Pol> o;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        o.v[c] = std::is_same<Pol, PolBF16>::value ? tb[(r0 + i) * kTbStride + 4 * kb + c]
+                                                   : tb[(r0 + i) * kTbStride + 4 * c + kb];
+    return o;
+}
+
+// acc[i][j] += sum_q A[q][i] B[q][j] over the tile's 16 queries.
+template <class Pol>
+__device__ __forceinline__ void wmma(typename Pol::Acc& acc, const WOp<Pol>& a, const WOp<Pol>& b) {
     if constexpr (std::is_same<Pol, PolBF16>::value) {
-        shortx4 a, b;
+        shortx4 x, y;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            a[e] = (short)f32_to_bf16(tb[(ra + i) * kTbStride + 4 * kb + e]);
-            b[e] = (short)f32_to_bf16(tb[(rb + i) * kTbStride + 4 * kb + e]);
+            x[e] = (short)f32_to_bf16(a.v[e]);
+            y[e] = (short)f32_to_bf16(b.v[e]);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, acc, 0, 0, 0);
     } else {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            acc = Pol::mma(tb[(ra + i) * kTbStride + 4 * c + kb], tb[(rb + i) * kTbStride + 4 * c + kb], acc);
+        for (int c = 0; c < 4; ++c) acc = Pol::mma(a.v[c], b.v[c], acc);
     }
 }
 
@@ -522,8 +539,11 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int 
 #pragma unroll
         for (int idx = 0; idx < 16; ++idx) tb[(16 + hid(idx, kb)) * kTbStride + j] = h2[idx];
         __builtin_amdgcn_wave_barrier();
+        {
+            const WOp<Pol> ga = wload<Pol>(tb, 0);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) wgrad<Pol>(w3[nt], tb, 0, 16 + 16 * nt);
+            for (int nt = 0; nt < 4; ++nt) wmma<Pol>(w3[nt], ga, wload<Pol>(tb, 16 + 16 * nt));
+        }
         __builtin_amdgcn_wave_barrier();
         // Stage 2: G2^T rows 0..63, H1^T rows 64..127 -> dW2.
 #pragma unroll
@@ -532,10 +552,17 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int 
             tb[(64 + hid(idx, kb)) * kTbStride + j] = h1[idx];
         }
         __builtin_amdgcn_wave_barrier();
+        {
+            WOp<Pol> hb[4];
 #pragma unroll
-        for (int mo = 0; mo < 4; ++mo)
+            for (int nt = 0; nt < 4; ++nt) hb[nt] = wload<Pol>(tb, 64 + 16 * nt);
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) wgrad<Pol>(w2[mo][nt], tb, 16 * mo, 64 + 16 * nt);
+            for (int mo = 0; mo < 4; ++mo) {
+                const WOp<Pol> ga = wload<Pol>(tb, 16 * mo);
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) wmma<Pol>(w2[mo][nt], ga, hb[nt]);
+            }
+        }
         __builtin_amdgcn_wave_barrier();
         // Stage 3: G1^T rows 0..63, F^T rows 64..(64 + 16 MF) -> dW1.
 #pragma unroll
@@ -546,10 +573,17 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int 
             if (k < 16 * Sh::MF) tb[(64 + k) * kTbStride + j] = fv[idx];
         }
         __builtin_amdgcn_wave_barrier();
+        {
+            WOp<Pol> fb[Sh::MF];
 #pragma unroll
-        for (int mo = 0; mo < 4; ++mo)
+            for (int nf = 0; nf < Sh::MF; ++nf) fb[nf] = wload<Pol>(tb, 64 + 16 * nf);
 #pragma unroll
-            for (int nf = 0; nf < Sh::MF; ++nf) wgrad<Pol>(w1[mo][nf], tb, 16 * mo, 64 + 16 * nf);
+            for (int mo = 0; mo < 4; ++mo) {
+                const WOp<Pol> ga = wload<Pol>(tb, 16 * mo);
+#pragma unroll
+                for (int nf = 0; nf < Sh::MF; ++nf) wmma<Pol>(w1[mo][nf], ga, fb[nf]);
+            }
+        }
         __builtin_amdgcn_wave_barrier();
     }
 

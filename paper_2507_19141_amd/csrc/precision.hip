@@ -46,3 +46,31 @@ hipError_t launch_count_nonfinite(const float* p, int64_t count, int32_t* counte
 }
 
 }  // namespace h4d
+
+namespace h4d {
+
+// Eq. 10: x' = x + dx, r' = r + dr, s' = s + ds from the decoder output delta
+// [n, out] (dx at columns 0..2, dr at 3..6, ds at 7..9).  One thread per Gaussian;
+// outputs may alias inputs.
+__global__ __launch_bounds__(256) void k_deform_apply(const float* __restrict__ delta, int n, int out,
+                                                      const float* x, const float* r, const float* s, float* xo,
+                                                      float* ro, float* so) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float* d = delta + (int64_t)i * out;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xo[(int64_t)i * 3 + k] = __fadd_rn(x[(int64_t)i * 3 + k], d[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ro[(int64_t)i * 4 + k] = __fadd_rn(r[(int64_t)i * 4 + k], d[3 + k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) so[(int64_t)i * 3 + k] = __fadd_rn(s[(int64_t)i * 3 + k], d[7 + k]);
+}
+
+hipError_t launch_deform_apply(const float* delta, int n, int out, const float* x, const float* r, const float* s,
+                               float* xo, float* ro, float* so, hipStream_t st) {
+    hipLaunchKernelGGL(k_deform_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, delta, n, out, x, r, s,
+                       xo, ro, so);
+    return hipGetLastError();
+}
+
+}  // namespace h4d

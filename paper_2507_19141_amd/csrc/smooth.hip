@@ -1,10 +1,10 @@
-// Spatio-temporal smoothness regulariser (DASH Section 4.3, Eq. 11), loss and table
-// gradient in one pass:
+// Spatio-temporal smoothness regulariser (DASH Section 4.3, Eq. 11), first pass:
 //   L_r = lam / n * sum_q || G(x_q) - G(clamp(x_q + eps_q)) ||^2
-//   dL/dtheta: +c d w at the corners of x, -c d w~ at the corners of x~, c = 2 lam / n.
-// Nothing is stored between the two encodes: both are recomputed per (query, level).
-// When x and x~ fall in the same hypervoxel (the common case for small eps) their
-// 16 corners coincide and one atomic per corner carries (w - w~).
+// and, when asked, the per-(query, level) difference d = G(x) - G(x~) written
+// level-major for the table-gradient pass (the tiled scatter with the pair of
+// corner sets, scaled by 2 lam / n).  Both encodes are recomputed per (query,
+// level); when x and x~ fall in the same hypervoxel their 16 corners coincide and
+// one gather per corner gives d with the weight difference w - w~.
 #include "h4d_device.h"
 
 namespace h4d {
@@ -17,7 +17,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth(DevGrid g, const TT* __
                                                          const float4* __restrict__ eps, int n,
                                                          typename AccOf<TT>::type lam_over_n,
                                                          typename AccOf<TT>::type* __restrict__ loss,
-                                                         typename AccOf<TT>::type* __restrict__ d_table) {
+                                                         typename AccOf<TT>::type* __restrict__ d_out) {
     using A = typename AccOf<TT>::type;
     __shared__ A red[kSmoothBlock / 64];
     const int l = blockIdx.y;
@@ -70,26 +70,10 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth(DevGrid g, const TT* __
         }
 #pragma unroll
         for (int f = 0; f < F; ++f) part += d[f] * d[f];
-        if (d_table) {
-            A gd[F];
+        if (d_out) {
+            A* o = d_out + ((int64_t)l * n + q) * F;
 #pragma unroll
-            for (int f = 0; f < F; ++f) gd[f] = A(2) * lam_over_n * d[f];
-            if (same) {
-#pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    const A dw = w0[k] - w1[k];
-#pragma unroll
-                    for (int f = 0; f < F; ++f) atomic_add(d_table + (size_t)r0[k] * F + f, dw * gd[f]);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 16; ++k)
-#pragma unroll
-                    for (int f = 0; f < F; ++f) {
-                        atomic_add(d_table + (size_t)r0[k] * F + f, w0[k] * gd[f]);
-                        atomic_add(d_table + (size_t)r1[k] * F + f, -(w1[k] * gd[f]));
-                    }
-            }
+            for (int f = 0; f < F; ++f) o[f] = d[f];
         }
     }
     // block sum of the squared differences, one atomic per block
@@ -105,7 +89,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth(DevGrid g, const TT* __
 
 template <typename TT>
 static hipError_t smooth_t(const DevGrid& g, const void* table, const float* xyzt, const float* eps, int n, double lam,
-                           void* loss, void* d_table, hipStream_t s) {
+                           void* loss, void* d_out, hipStream_t s) {
     using A = typename AccOf<TT>::type;
     const dim3 grid((unsigned)((n + kSmoothBlock - 1) / kSmoothBlock), (unsigned)g.L), block(kSmoothBlock);
     const TT* t = static_cast<const TT*>(table);
@@ -113,23 +97,23 @@ static hipError_t smooth_t(const DevGrid& g, const void* table, const float* xyz
     const float4* e = reinterpret_cast<const float4*>(eps);
     const A c = (A)(lam / (double)n);
     A* lo = static_cast<A*>(loss);
-    A* dt = static_cast<A*>(d_table);
+    A* dd = static_cast<A*>(d_out);
     switch (g.F) {
-        case 1: hipLaunchKernelGGL((k_smooth<TT, 1>), grid, block, 0, s, g, t, x, e, n, c, lo, dt); break;
-        case 2: hipLaunchKernelGGL((k_smooth<TT, 2>), grid, block, 0, s, g, t, x, e, n, c, lo, dt); break;
-        case 4: hipLaunchKernelGGL((k_smooth<TT, 4>), grid, block, 0, s, g, t, x, e, n, c, lo, dt); break;
-        case 8: hipLaunchKernelGGL((k_smooth<TT, 8>), grid, block, 0, s, g, t, x, e, n, c, lo, dt); break;
+        case 1: hipLaunchKernelGGL((k_smooth<TT, 1>), grid, block, 0, s, g, t, x, e, n, c, lo, dd); break;
+        case 2: hipLaunchKernelGGL((k_smooth<TT, 2>), grid, block, 0, s, g, t, x, e, n, c, lo, dd); break;
+        case 4: hipLaunchKernelGGL((k_smooth<TT, 4>), grid, block, 0, s, g, t, x, e, n, c, lo, dd); break;
+        case 8: hipLaunchKernelGGL((k_smooth<TT, 8>), grid, block, 0, s, g, t, x, e, n, c, lo, dd); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_smoothness(const DevGrid& g, h4d_dtype dt, const void* table, const float* xyzt, const float* eps,
-                             int n, double lam, void* loss, void* d_table, hipStream_t s) {
+                             int n, double lam, void* loss, void* d_out, hipStream_t s) {
     switch (dt) {
-        case H4D_F32: return smooth_t<float>(g, table, xyzt, eps, n, lam, loss, d_table, s);
-        case H4D_BF16: return smooth_t<bf16_t>(g, table, xyzt, eps, n, lam, loss, d_table, s);
-        case H4D_F64: return smooth_t<double>(g, table, xyzt, eps, n, lam, loss, d_table, s);
+        case H4D_F32: return smooth_t<float>(g, table, xyzt, eps, n, lam, loss, d_out, s);
+        case H4D_BF16: return smooth_t<bf16_t>(g, table, xyzt, eps, n, lam, loss, d_out, s);
+        case H4D_F64: return smooth_t<double>(g, table, xyzt, eps, n, lam, loss, d_out, s);
     }
     return hipErrorInvalidValue;
 }

@@ -57,7 +57,9 @@ def run_smooth(lg, dt, table_dev, x, eps, lam, E, F, want_grad=True):
     tdt = torch.float64 if dt == _lib.F64 else torch.float32
     loss = torch.zeros(1, dtype=tdt, device="cuda")
     d_table = torch.zeros((E, F), dtype=tdt, device="cuda") if want_grad else None
-    _lib.smoothness_reg(lg, dt, table_dev, dev(x), dev(eps), x.shape[0], lam, loss, d_table)
+    wb = _lib.smoothness_workspace_bytes(lg, dt, x.shape[0])
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    _lib.smoothness_reg(lg, dt, table_dev, dev(x), dev(eps), x.shape[0], lam, loss, d_table, ws, wb)
     return float(host(loss)[0]), (host(d_table) if want_grad else None)
 
 

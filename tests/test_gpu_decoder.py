@@ -250,3 +250,21 @@ def test_deform_path_paper_scene_full_size():
     rhs = float(np.sum(O.encode(x, u, og) * rf))
     scale = float(np.sum(O.encode(x, np.abs(u), og) * sf))
     assert abs(lhs - rhs) <= RTOL_GRAD * scale
+
+
+def test_deform_apply_eq10_bit_exact():
+    import torch
+    rng = np.random.default_rng(110)
+    n = 5000 + 3
+    delta = rng.standard_normal((n, 10)).astype(np.float32)
+    x, r, s = (rng.standard_normal((n, k)).astype(np.float32) for k in (3, 4, 3))
+    xo, ro, so = (torch.empty((n, k), device="cuda") for k in (3, 4, 3))
+    _lib.hash4d_deform_apply(dev(delta), n, 10, dev(x), dev(r), dev(s), xo, ro, so)
+    ref = O.deform(x, r, s, delta)
+    for got, want in zip((xo, ro, so), ref):
+        # one FP32 add each: bit-exact against the FP64 sum rounded to FP32
+        assert np.array_equal(host(got), want.astype(np.float32))
+    # in place
+    xd = dev(x)
+    _lib.hash4d_deform_apply(dev(delta), n, 10, xd, dev(r), dev(s), xd, ro, so)
+    assert np.array_equal(host(xd), ref[0].astype(np.float32))
