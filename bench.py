@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-probes", action="store_true", help="skip the roofline probes")
     ap.add_argument("--no-batched", action="store_true", help="skip the multi-scene form")
+    ap.add_argument("--probe-sweep", action="store_true",
+                    help="only run the gather / atomic probes over several footprints and print them")
     ap.add_argument("--cpu-sample", type=int, default=40000, help="queries the CPU oracle is timed on")
     return ap.parse_args()
 
@@ -193,6 +195,40 @@ def probes(torch, _lib, E, F, n_loads, reps=5):
     return out
 
 
+def probe_sweep(torch, _lib, E, n_loads, reps=5):
+    """Random FP32 atomics and random gathers over a range of footprints, both atomic
+    modes (any row / rows of lines owned by the workgroup's XCC)."""
+    buf = torch.zeros((E, 2), device="cuda")
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(reps):
+            fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps / 1e3
+    rows_list = [1 << 17, 1 << 19, 1 << 21, E]
+    out = {"n": n_loads, "scatter": [], "gather": []}
+    for rows in rows_list:
+        for mode in (0, 1):
+            t = timed(lambda: _lib.h4d_probe_scatter(buf, rows, n_loads, 9, mode))
+            out["scatter"].append({"rows": rows, "MiB": rows * 8 / 2 ** 20, "mode": mode, "ms": t * 1e3,
+                                   "G_atomics_per_s": 2 * n_loads / t / 1e9})
+        t = timed(lambda: _lib.h4d_probe_gather(buf, rows, 8, n_loads, 7, buf))
+        out["gather"].append({"rows": rows, "MiB": rows * 8 / 2 ** 20, "ms": t * 1e3, "GBps": n_loads * 8 / t / 1e9,
+                              "G_loads_per_s": n_loads / t / 1e9})
+    for mode in (0, 1):
+        buf.zero_()
+        _lib.h4d_probe_scatter(buf, E, n_loads, 9, mode)
+        torch.cuda.synchronize()
+        out[f"scatter_sum_mode{mode}"] = float(buf.double().sum())
+    out["scatter_sum_expected"] = 2.0 * n_loads
+    return out
+
+
 def cpu_baseline(sample: int):
     import numpy as np
     from threadpoolctl import threadpool_limits
@@ -321,6 +357,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     _lib.load()
+    if args.probe_sweep:
+        w = synth.PAPER_SCENE
+        E = _lib.h4d_grid_init(w.L, w.F, _lib.h4d_grid_schedule(w.L, *w.space),
+                               _lib.h4d_grid_schedule(w.L, *w.time), w.T).E
+        print(json.dumps({"probe_sweep": probe_sweep(torch, _lib, E, w.n * 16 * w.L)}), flush=True)
+        return
 
     fp32 = Path(torch, _lib, synth, "fp32")
     wall, gpu_ms, per = fp32.run(args.steps, args.warmup)
