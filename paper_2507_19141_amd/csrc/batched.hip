@@ -101,19 +101,21 @@ struct BTile {
     uint32_t base, cnt;  // table rows [base, base + cnt)
 };
 
+constexpr int kBatchScatterBlock = 1024;  // one workgroup per CU (128 KiB tile), 16 wavefronts
+
 template <int F>
-__global__ __launch_bounds__(kBatchBlock) void k_bscatter(const BSeg* __restrict__ segs, const DevGrid* __restrict__ grids,
+__global__ __launch_bounds__(kBatchScatterBlock) void k_bscatter(const BSeg* __restrict__ segs, const DevGrid* __restrict__ grids,
                                                           const BTile* __restrict__ tiles, float scale) {
     extern __shared__ __align__(16) unsigned char smem[];
     float* tile = reinterpret_cast<float*>(smem);
     const BTile tl = tiles[blockIdx.x];
     const DevGrid& g = grids[tl.scene];
     const int l = tl.level;
-    for (uint32_t i = threadIdx.x; i < tl.cnt * F; i += kBatchBlock) tile[i] = 0.f;
+    for (uint32_t i = threadIdx.x; i < tl.cnt * F; i += kBatchScatterBlock) tile[i] = 0.f;
     __syncthreads();
     for (int sgi = tl.seg0; sgi < tl.seg0 + tl.nseg; ++sgi) {
         const BSeg sg = segs[sgi];
-        for (int q = threadIdx.x; q < sg.n; q += kBatchBlock) {
+        for (int q = threadIdx.x; q < sg.n; q += kBatchScatterBlock) {
             const float* gp = sg.d_feat + ((int64_t)l * sg.n + q) * F;
             float gv[F];
 #pragma unroll
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_bscatter(const BSeg* __restrict
     }
     __syncthreads();
     float* out = segs[tl.seg0].d_table + (size_t)tl.base * F;
-    for (uint32_t i = threadIdx.x; i < tl.cnt * F; i += kBatchBlock) {
+    for (uint32_t i = threadIdx.x; i < tl.cnt * F; i += kBatchScatterBlock) {
         const float v = tile[i];
         if (v != 0.f) out[i] += v;
     }
@@ -237,7 +239,7 @@ static hipError_t launch_bscatter(const h4d_batched_plan& p, float scale, hipStr
     if (p.ntiles == 0) return hipSuccess;
     const int F = p.scenes[0].grid.F;
     const size_t lds = (size_t)kTileBytes;
-    const dim3 grid(p.ntiles), block(kBatchBlock);
+    const dim3 grid(p.ntiles), block(kBatchScatterBlock);
 #define H4D_BSCA(FF)                                                                                             \
     do {                                                                                                         \
         hipError_t e = hipFuncSetAttribute((const void*)k_bscatter<FF>, hipFuncAttributeMaxDynamicSharedMemorySize, \

@@ -57,8 +57,12 @@ __global__ __launch_bounds__(kEncodeBlock) void k_encode(DevGrid g, const TT* __
 // a hashed level share a tile, so a query touches at most 8 tiles per level.
 // PAIR: each query also subtracts the same gradient at the corners of x + eps (the
 // second term of Eq. 11).
+// 1024 threads share each tile: the 128 KiB of LDS allows one workgroup per CU, and
+// sixteen wavefronts (four per SIMD) keep the query loads in flight.
+constexpr int kScatterBlock = 1024;
+
 template <typename G, int F, bool PAIR>
-__global__ __launch_bounds__(kEncodeBlock) void k_scatter_tiled(DevGrid g, TileMap tm, const float4* __restrict__ xyzt,
+__global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, TileMap tm, const float4* __restrict__ xyzt,
                                                                 const float4* __restrict__ eps, int n,
                                                                 const G* __restrict__ src, int64_t lstride,
                                                                 int64_t qstride, G scale, G* __restrict__ d_table) {
@@ -69,9 +73,9 @@ __global__ __launch_bounds__(kEncodeBlock) void k_scatter_tiled(DevGrid g, TileM
     const uint32_t first = (uint32_t)((int)blockIdx.x - tm.tile_start[l]) * (uint32_t)tm.rows_per_tile;
     const uint32_t base = g.off[l] + first;
     const uint32_t cnt = min((uint32_t)tm.rows_per_tile, (uint32_t)tm.level_rows[l] - first);
-    for (uint32_t i = threadIdx.x; i < cnt * F; i += kEncodeBlock) tile[i] = G(0);
+    for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) tile[i] = G(0);
     __syncthreads();
-    for (int q = threadIdx.x; q < n; q += kEncodeBlock) {
+    for (int q = threadIdx.x; q < n; q += kScatterBlock) {
         const G* gp = src + (int64_t)l * lstride + (int64_t)q * qstride;
         G gv[F];
 #pragma unroll
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(kEncodeBlock) void k_scatter_tiled(DevGrid g, TileM
     }
     __syncthreads();
     G* out = d_table + (size_t)base * F;
-    for (uint32_t i = threadIdx.x; i < cnt * F; i += kEncodeBlock) {
+    for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) {
         const G v = tile[i];
         if (v != G(0)) out[i] += v;
     }
@@ -167,7 +171,7 @@ static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt
     const size_t lds = (size_t)tm.rows_per_tile * F * sizeof(G);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(tm.tile_start[g.L]), dim3(kEncodeBlock), lds, s, g, tm,
+    hipLaunchKernelGGL(kern, dim3(tm.tile_start[g.L]), dim3(kScatterBlock), lds, s, g, tm,
                        reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n,
                        static_cast<const G*>(src), ls, qs, (G)scale, static_cast<G*>(d_table));
     return hipGetLastError();

@@ -234,10 +234,15 @@ struct Frags {
 
 template <class Pol, int IN>
 __device__ void fill_frags(typename Pol::FE* lds, int count, const typename Pol::S* __restrict__ params, int out,
-                           const ParamOff& po) {
+                           const ParamOff& po, typename Pol::S* stage) {
+    // One coalesced burst of the parameters into LDS first (many loads in flight),
+    // then the fragment permutation reads LDS only.
+#pragma unroll 8
+    for (int i = threadIdx.x; i < po.P; i += blockDim.x) stage[i] = params[i];
+    __syncthreads();
     for (int t = threadIdx.x; t < count; t += blockDim.x) {
         const int s = frag_source<Pol, IN>(t, out, po);
-        lds[t] = s >= 0 ? Pol::to_frag(params[s]) : typename Pol::FE(0);
+        lds[t] = s >= 0 ? Pol::to_frag(stage[s]) : typename Pol::FE(0);
     }
 }
 
@@ -335,7 +340,11 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(MlpBatch batch, int o
     const typename Pol::S* __restrict__ params = static_cast<const typename Pol::S*>(sp.params);
     const ParamOff po(IN, out);
     Frags<Pol, IN, kLds> fr{reinterpret_cast<const typename Pol::FE*>(smem), params, out, po};
-    if constexpr (kLds) fill_frags<Pol, IN>(reinterpret_cast<typename Pol::FE*>(smem), Sh::FWD_FRAGS, params, out, po);
+    if constexpr (kLds) {
+        const size_t fbytes = ((size_t)Sh::FWD_FRAGS * sizeof(typename Pol::FE) + 15) / 16 * 16;
+        fill_frags<Pol, IN>(reinterpret_cast<typename Pol::FE*>(smem), Sh::FWD_FRAGS, params, out, po,
+                            reinterpret_cast<typename Pol::S*>(smem + fbytes));
+    }
     __syncthreads();
     V b1[16], b2[16], b3[4];
     load_biases<Pol>(params, po, out, b1, b2, b3);
@@ -427,7 +436,9 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int 
 
     Frags<Pol, IN, kLds> fr{frag_lds, params, out, po};
     if constexpr (kLds) {
-        fill_frags<Pol, IN>(frag_lds, Sh::ALL_FRAGS, params, out, po);
+        // the gradient accumulator doubles as the staging buffer of the parameters
+        fill_frags<Pol, IN>(frag_lds, Sh::ALL_FRAGS, params, out, po, reinterpret_cast<typename Pol::S*>(wacc));
+        __syncthreads();
         for (int t = threadIdx.x; t < po.P; t += blockDim.x) wacc[t] = G(0);
     }
     __syncthreads();
@@ -691,9 +702,11 @@ static int mlp_blocks(int n, int cap) {
 }
 
 template <class Pol, int IN>
-static size_t lds_forward() {
+static size_t lds_forward(int out) {
     if (std::is_same<Pol, PolF64>::value) return 0;
-    return (size_t)Shape<Pol, IN>::FWD_FRAGS * sizeof(typename Pol::FE);
+    const ParamOff po(IN, out);
+    return ((size_t)Shape<Pol, IN>::FWD_FRAGS * sizeof(typename Pol::FE) + 15) / 16 * 16 +
+           (size_t)po.P * sizeof(typename Pol::S);
 }
 
 template <class Pol, int IN>
@@ -714,7 +727,7 @@ size_t mlp_workspace_bytes(h4d_dtype dt, int in, int out, int n) {
 
 template <class Pol, int IN>
 static hipError_t forward_t(const MlpBatch& b, int blocks, int out, hipStream_t s) {
-    const size_t lds = lds_forward<Pol, IN>();
+    const size_t lds = lds_forward<Pol, IN>(out);
     auto kern = k_mlp_forward<Pol, IN>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
