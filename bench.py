@@ -83,6 +83,8 @@ class Path:
         self.dt = _lib.BF16 if form == "bf16" else _lib.F32
         self.ws_bytes = _lib.deform_mlp_workspace_bytes(self.m, self.dt, n)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+        self.sws_bytes = _lib.hash4d_encode_backward_workspace_bytes(self.g, n)
+        self.sws = torch.empty(self.sws_bytes, dtype=torch.uint8, device="cuda")
         if form == "bf16":
             self.table_lo = torch.empty(E * F, dtype=torch.int16, device="cuda")
             self.params_lo = torch.empty(params.size, dtype=torch.int16, device="cuda")
@@ -119,7 +121,8 @@ class Path:
         L_.deform_mlp_backward(self.m, self.dt, params, self.feat, self.n, self.d_delta, S, 1.0 / S, self.d_feat,
                                self.d_params, self.ws, self.ws_bytes, LM, F)
         mark()
-        L_.hash4d_encode_backward(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0 / S, self.d_table, LM)
+        L_.hash4d_encode_backward(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0 / S, self.d_table, self.sws,
+                                  self.sws_bytes, LM)
         if self.form == "bf16":
             L_.h4d_count_nonfinite(self.d_table, self.E * F, self.counter)
             L_.h4d_count_nonfinite(self.d_params, self.d_params.numel(), self.counter)

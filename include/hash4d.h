@@ -128,10 +128,14 @@ h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* tabl
  *   d_feat  n L F values in `layout`     d_table [E, F] (+=)
  * Owner-computes scatter: one workgroup per (level, tile of consecutive table rows)
  * sums its rows' updates in LDS and adds them to d_table; no device-wide atomics.
- * LDS atomics make the summation order, hence the last bits, vary run to run. */
+ * A pre-pass writes a per-(query, level) mask of touched tiles into `workspace`
+ * (device, at least hash4d_encode_backward_workspace_bytes) so that each tile only
+ * works on the queries that reach it.  LDS atomics make the summation order, hence
+ * the last bits, vary run to run. */
+size_t hash4d_encode_backward_workspace_bytes(const h4d_grid* g, int64_t n);
 h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
                                   h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
-                                  void* stream);
+                                  void* workspace, size_t ws_bytes, void* stream);
 
 /* Test hook: the table row (level offset included) and FP32 weight of the 16
  * corners of every query and level.  Corner c is upper along x, y, z, t iff bit
@@ -156,8 +160,8 @@ h4d_status hash4d_deform_apply(const float* delta, int64_t n, int32_t out, const
  *   d_table += (2 lambda / n) (d w at x's corners - d w~ at x~'s corners)
  * Both encodes are recomputed per query and level, nothing is kept between calls.
  * d_table may be NULL (loss only, no workspace needed).  Otherwise `workspace`
- * (device, smoothness_workspace_bytes) receives d, and the gradient is added by
- * the tiled scatter.  table_dt as hash4d_encode; loss and d_table are FP32 (FP64
+ * (device, smoothness_workspace_bytes) receives d and the scatter's tile masks, and
+ * the gradient is added by the tiled scatter.  table_dt as hash4d_encode; loss and d_table are FP32 (FP64
  * for F64).  eps: FP32 [n, 4], 16-byte aligned. */
 size_t smoothness_workspace_bytes(const h4d_grid* g, h4d_dtype table_dt, int64_t n);
 h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* table, const float* xyzt,
@@ -209,8 +213,8 @@ h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* param
 
 /* -------------------------------------------------- deformation path ---- */
 
-/* Workspace of hash4d_deform_backward: decoder partials plus the [L, n, F]
- * feature gradient.  0 if the arguments are invalid. */
+/* Workspace of hash4d_deform_backward: decoder partials, the [L, n, F] feature
+ * gradient and the scatter's tile masks.  0 if the arguments are invalid. */
 size_t hash4d_deform_workspace_bytes(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, int64_t n);
 
 /* Whole forward of the deformation field for n dynamic Gaussians at their

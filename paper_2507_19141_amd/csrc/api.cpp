@@ -111,10 +111,12 @@ static h4d_status check_mlp(const h4d_mlp* m, h4d_dtype dt) {
     return check_dtype(dt);
 }
 
+// Deformation backward workspace: [decoder partials | d_feat [L, n, F] | tile masks].
 static size_t deform_ws(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, int64_t n) {
     const size_t el = dt == H4D_F64 ? sizeof(double) : sizeof(float);
     const size_t a = (mlp_workspace_bytes(dt, m->in, m->out, (int)n) + 255) / 256 * 256;
-    return a + (size_t)n * g->L * g->F * el;
+    const size_t b = ((size_t)n * g->L * g->F * el + 255) / 256 * 256;
+    return a + b + scatter_mask_bytes((int)n, g->L);
 }
 
 h4d_status validate_grid(const h4d_grid* g) { return check_grid(g); }
@@ -231,9 +233,14 @@ h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* tabl
                       "hash4d_encode");
 }
 
+size_t hash4d_encode_backward_workspace_bytes(const h4d_grid* g, int64_t n) {
+    if (check_grid(g) != H4D_OK || n < 0 || n > kMaxN || n * (int64_t)g->L > kMaxN) return 0;
+    return scatter_mask_bytes((int)n, g->L);
+}
+
 h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
                                   h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
-                                  void* stream) {
+                                  void* workspace, size_t ws_bytes, void* stream) {
     g_last_error.clear();
     h4d_status st;
     int64_t ls, qs;
@@ -242,11 +249,14 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
     if ((st = feat_strides(layout, n, g->L, g->F, &ls, &qs))) return st;
     if (n == 0) return H4D_OK;
     if (!d_feat || !d_table) return fail(H4D_EINVAL, "d_feat or d_table is NULL");
+    const size_t need = scatter_mask_bytes((int)n, g->L);
+    if (!workspace || ws_bytes < need)
+        return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
     const DevGrid d = to_device(*g);
     int64_t rows[H4D_MAX_LEVELS];
     rows_of(*g, rows);
     return hip_status(launch_scatter_tiled(d, rows, grad_dt, xyzt, nullptr, (int)n, d_feat, ls, qs,
-                                           (double)grad_scale, d_table, (hipStream_t)stream),
+                                           (double)grad_scale, d_table, workspace, (hipStream_t)stream),
                       "hash4d_encode_backward");
 }
 
@@ -262,9 +272,16 @@ h4d_status hash4d_corner_indices(const h4d_grid* g, const float* xyzt, int64_t n
     return hip_status(launch_corner_indices(d, xyzt, (int)n, rows, w, (hipStream_t)stream), "hash4d_corner_indices");
 }
 
+// Smoothness workspace: [d = G(x) - G(x + eps), level-major | tile masks].
+static size_t smooth_ws(const h4d_grid* g, h4d_dtype table_dt, int64_t n) {
+    const size_t d = ((size_t)n * g->L * g->F * (table_dt == H4D_F64 ? sizeof(double) : sizeof(float)) + 255) / 256 * 256;
+    return d + scatter_mask_bytes((int)n, g->L);
+}
+
 size_t smoothness_workspace_bytes(const h4d_grid* g, h4d_dtype table_dt, int64_t n) {
     if (check_grid(g) != H4D_OK || check_dtype(table_dt) != H4D_OK || n < 0 || n > kMaxN) return 0;
-    return (size_t)n * g->L * g->F * (table_dt == H4D_F64 ? sizeof(double) : sizeof(float));
+    if (n * (int64_t)g->L * g->F > kMaxN) return 0;
+    return smooth_ws(g, table_dt, n);
 }
 
 h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* table, const float* xyzt,
@@ -277,7 +294,7 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
     if (!table || !eps || !loss) return fail(H4D_EINVAL, "table, eps or loss is NULL");
     if (((uintptr_t)eps) & 15u) return fail(H4D_EINVAL, "eps is not 16-byte aligned");
     if (n * (int64_t)g->L * g->F > kMaxN) return fail(H4D_EINVAL, "n L F exceeds 2^31-1 features");
-    const size_t need = (size_t)n * g->L * g->F * (table_dt == H4D_F64 ? sizeof(double) : sizeof(float));
+    const size_t need = smooth_ws(g, table_dt, n);
     if (d_table && (!workspace || ws_bytes < need))
         return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
     const DevGrid d = to_device(*g);
@@ -291,8 +308,11 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
     // pass 2: d_table += (2 lambda / n) (d at x's corners - d at x~'s corners)
     int64_t rows[H4D_MAX_LEVELS];
     rows_of(*g, rows);
+    const size_t dbytes =
+        ((size_t)n * g->L * g->F * (table_dt == H4D_F64 ? sizeof(double) : sizeof(float)) + 255) / 256 * 256;
     return hip_status(launch_scatter_tiled(d, rows, table_dt == H4D_F64 ? H4D_F64 : H4D_F32, xyzt, eps, (int)n,
-                                           workspace, n * g->F, g->F, 2.0 * (double)lambda / (double)n, d_table, s),
+                                           workspace, n * g->F, g->F, 2.0 * (double)lambda / (double)n, d_table,
+                                           static_cast<char*>(workspace) + dbytes, s),
                       "smoothness_reg/scatter");
 }
 
@@ -463,8 +483,10 @@ h4d_status hash4d_deform_backward(const h4d_grid* g, const h4d_mlp* m, h4d_dtype
     const hipStream_t s = (hipStream_t)stream;
     const int64_t ls = n * g->F, qs = g->F;
     char* ws = static_cast<char*>(workspace);
+    const size_t el = dt == H4D_F64 ? sizeof(double) : sizeof(float);
     const size_t part = (mlp_workspace_bytes(dt, m->in, m->out, (int)n) + 255) / 256 * 256;
     void* d_feat = ws + part;
+    void* masks = ws + part + ((size_t)n * g->L * g->F * el + 255) / 256 * 256;
     // decoder backward: d_feat keeps the loss scale, d_params gets grad_scale
     if ((st = hip_status(launch_mlp_backward(dt, m->in, m->out, params, feat, g->F, ls, qs, (int)n, d_delta,
                                              loss_scale, 1.0, grad_scale, d_feat, ls, qs, d_params, ws, s),
@@ -473,7 +495,7 @@ h4d_status hash4d_deform_backward(const h4d_grid* g, const h4d_mlp* m, h4d_dtype
     int64_t rows[H4D_MAX_LEVELS];
     rows_of(*g, rows);
     return hip_status(launch_scatter_tiled(d, rows, dt == H4D_F64 ? H4D_F64 : H4D_F32, xyzt, nullptr, (int)n, d_feat,
-                                           ls, qs, grad_scale, d_table, s),
+                                           ls, qs, grad_scale, d_table, masks, s),
                       "hash4d_deform_backward/encode");
 }
 

@@ -29,6 +29,7 @@ struct BSeg {
     float* feat;         // [L, n, F]
     const float* d_feat; // [L, n, F]
     float* d_table;      // [E, F] FP32, +=
+    uint32_t* mask;      // [L, n] tile masks of the scatter
 };
 
 struct BRange {          // items [first, first + ntiles) belong to (seg, level group lg)
@@ -95,27 +96,42 @@ __global__ __launch_bounds__(kBatchBlock) void k_bencode(const BSeg* __restrict_
 }
 
 // One workgroup per (scene, level, tile of rows): the owner-computes scatter of the
-// plain path, scanning every timestamp segment of its scene.
+// plain path over every timestamp segment of its scene, each segment's queries
+// filtered by the tile masks of k_bmask.
 struct BTile {
     int scene, level, seg0, nseg;
     uint32_t base, cnt;  // table rows [base, base + cnt)
+    uint32_t bit;        // the tile's bit in the query masks
 };
+
+__global__ __launch_bounds__(kBatchBlock) void k_bmask(const BSeg* __restrict__ segs, const DevGrid* __restrict__ grids,
+                                                       const TileMap* __restrict__ tms) {
+    const BSeg sg = segs[blockIdx.z];
+    const int l = blockIdx.y;
+    const int q = blockIdx.x * kBatchBlock + (int)threadIdx.x;
+    const DevGrid& g = grids[sg.scene];
+    if (q >= sg.n || l >= g.L) return;
+    float4 x = sg.xyz[q];
+    x.w = sg.t;
+    sg.mask[(int64_t)l * sg.n + q] = corner_tile_mask(g, tms[sg.scene], l, x);
+}
 
 constexpr int kBatchScatterBlock = 1024;  // one workgroup per CU (128 KiB tile), 16 wavefronts
 
 template <int F>
 __global__ __launch_bounds__(kBatchScatterBlock) void k_bscatter(const BSeg* __restrict__ segs, const DevGrid* __restrict__ grids,
-                                                          const BTile* __restrict__ tiles, float scale) {
+                                                                 const BTile* __restrict__ tiles, float scale) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int queue[2 * kBatchScatterBlock];
+    __shared__ int qcount;
     float* tile = reinterpret_cast<float*>(smem);
     const BTile tl = tiles[blockIdx.x];
     const DevGrid& g = grids[tl.scene];
     const int l = tl.level;
     for (uint32_t i = threadIdx.x; i < tl.cnt * F; i += kBatchScatterBlock) tile[i] = 0.f;
-    __syncthreads();
     for (int sgi = tl.seg0; sgi < tl.seg0 + tl.nseg; ++sgi) {
         const BSeg sg = segs[sgi];
-        for (int q = threadIdx.x; q < sg.n; q += kBatchScatterBlock) {
+        masked_queue_loop<kBatchScatterBlock>(sg.n, sg.mask + (int64_t)l * sg.n, tl.bit, queue, &qcount, [&](int q) {
             const float* gp = sg.d_feat + ((int64_t)l * sg.n + q) * F;
             float gv[F];
 #pragma unroll
@@ -123,9 +139,8 @@ __global__ __launch_bounds__(kBatchScatterBlock) void k_bscatter(const BSeg* __r
             float4 x = sg.xyz[q];
             x.w = sg.t;
             tile_contrib<float, F>(g, l, x, gv, tl.base, tl.cnt, tile);
-        }
+        });
     }
-    __syncthreads();
     float* out = segs[tl.seg0].d_table + (size_t)tl.base * F;
     for (uint32_t i = threadIdx.x; i < tl.cnt * F; i += kBatchScatterBlock) {
         const float v = tile[i];
@@ -158,6 +173,9 @@ struct h4d_batched_plan {
     BRange* ranges_enc = nullptr;
     BTile* tiles = nullptr;
     int ntiles = 0;
+    TileMap* tms = nullptr;
+    uint32_t* masks = nullptr;
+    int max_n = 0, max_L = 0;
     int nranges_enc = 0, total_enc = 0;
     float* d_feat = nullptr;
     void* ws = nullptr;
@@ -237,6 +255,13 @@ static hipError_t launch_bencode(const h4d_batched_plan& p, const BSchedule& s, 
 
 static hipError_t launch_bscatter(const h4d_batched_plan& p, float scale, hipStream_t st) {
     if (p.ntiles == 0) return hipSuccess;
+    if (p.max_n > 0) {
+        hipLaunchKernelGGL(k_bmask, dim3((unsigned)((p.max_n + kBatchBlock - 1) / kBatchBlock), (unsigned)p.max_L,
+                                         (unsigned)p.nseg),
+                           dim3(kBatchBlock), 0, st, p.segs, p.grids, p.tms);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const int F = p.scenes[0].grid.F;
     const size_t lds = (size_t)kTileBytes;
     const dim3 grid(p.ntiles), block(kBatchScatterBlock);
@@ -468,6 +493,11 @@ h4d_status hash4d_batched_plan_create(h4d_batched_plan** out, const h4d_scene_de
     }
     hipError_t e = hipMalloc((void**)&p->d_feat, std::max<int64_t>(dfeat_elems, 1) * sizeof(float));
     if (e != hipSuccess) return bail(plan_hip(e, "plan d_feat"));
+    int64_t mask_elems = 0;
+    for (int s = 0; s < n_scenes; ++s) mask_elems += (int64_t)scenes[s].n_times * scenes[s].grid.L * scenes[s].n;
+    if ((e = hipMalloc((void**)&p->masks, std::max<int64_t>(mask_elems, 1) * sizeof(uint32_t))) != hipSuccess)
+        return bail(plan_hip(e, "plan masks"));
+    int64_t mo = 0;
     int64_t dfo = 0;
     for (int s = 0; s < n_scenes; ++s) {
         const h4d_scene_desc& d = scenes[s];
@@ -482,6 +512,8 @@ h4d_status hash4d_batched_plan_create(h4d_batched_plan** out, const h4d_scene_de
             b.feat = d.feat + k * seg_elems;
             b.d_feat = p->d_feat + dfo + k * seg_elems;
             b.d_table = d.d_table;
+            b.mask = p->masks + mo;
+            mo += (int64_t)d.grid.L * d.n;
             segs.push_back(b);
         }
         dfo += d.n_times * seg_elems;
@@ -496,20 +528,31 @@ h4d_status hash4d_batched_plan_create(h4d_batched_plan** out, const h4d_scene_de
     // scatter tiles: (scene, level, rows) with at most kTileBytes of FP32 rows each
     {
         std::vector<BTile> tiles;
+        std::vector<TileMap> tms;
         int seg0 = 0;
         for (int sc = 0; sc < n_scenes; ++sc) {
             const h4d_scene_desc& d = scenes[sc];
-            const int rpt = kTileBytes / (d.grid.F * (int)sizeof(float));
+            int64_t lrows[H4D_MAX_LEVELS];
+            for (int l = 0; l < d.grid.L; ++l) lrows[l] = d.grid.offset[l + 1] - d.grid.offset[l];
+            const TileMap tm = make_tile_map(p->grids_h[sc], lrows, d.grid.F, (int)sizeof(float));
+            tms.push_back(tm);
             for (int l = 0; l < d.grid.L; ++l) {
-                const int64_t r0 = d.grid.offset[l], r1 = d.grid.offset[l + 1];
-                for (int64_t r = r0; r < r1; r += rpt)
-                    tiles.push_back(BTile{sc, l, seg0, d.n_times, (uint32_t)r, (uint32_t)std::min<int64_t>(rpt, r1 - r)});
+                const int P = tm.tile_start[l + 1] - tm.tile_start[l];
+                for (int t = 0; t < P; ++t) {
+                    const int64_t r = d.grid.offset[l] + (int64_t)t * tm.rows_per_tile;
+                    const uint32_t cnt = (uint32_t)std::min<int64_t>(tm.rows_per_tile, d.grid.offset[l + 1] - r);
+                    tiles.push_back(BTile{sc, l, seg0, d.n_times, (uint32_t)r, cnt, 1u << ((t * 32) / P)});
+                }
             }
             seg0 += d.n_times;
+            p->max_n = std::max(p->max_n, (int)d.n);
+            p->max_L = std::max(p->max_L, (int)d.grid.L);
         }
         p->ntiles = (int)tiles.size();
         if ((e = hipMalloc((void**)&p->tiles, std::max<size_t>(1, tiles.size()) * sizeof(BTile))) != hipSuccess ||
-            (e = hipMemcpy(p->tiles, tiles.data(), tiles.size() * sizeof(BTile), hipMemcpyHostToDevice)) != hipSuccess)
+            (e = hipMemcpy(p->tiles, tiles.data(), tiles.size() * sizeof(BTile), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMalloc((void**)&p->tms, tms.size() * sizeof(TileMap))) != hipSuccess ||
+            (e = hipMemcpy(p->tms, tms.data(), tms.size() * sizeof(TileMap), hipMemcpyHostToDevice)) != hipSuccess)
             return bail(plan_hip(e, "plan tiles"));
     }
     // decoder spans
@@ -601,6 +644,8 @@ void hash4d_batched_plan_destroy(h4d_batched_plan* p) {
     hipFree(p->segs);
     hipFree(p->ranges_enc);
     hipFree(p->tiles);
+    hipFree(p->tms);
+    hipFree(p->masks);
     hipFree(p->d_feat);
     hipFree(p->ws);
     delete p;

@@ -51,48 +51,85 @@ __global__ __launch_bounds__(kEncodeBlock) void k_encode(DevGrid g, const TT* __
 // second whatever the footprint (they are not executed in the XCD-local L2), so
 // the scatter avoids them altogether.  Owner computes: one workgroup per (level,
 // tile of R consecutive table rows of that level) keeps the tile's gradient in LDS,
-// scans every query of the level, adds w_c g for the corners that fall in its tile
-// with LDS atomics, and finally adds the tile to d_table with plain loads and
-// stores (no other workgroup owns those rows).  With pi_1 = 1 the two x-corners of
-// a hashed level share a tile, so a query touches at most 8 tiles per level.
+// adds w_c g for the corners of the level's queries that fall in its tile with LDS
+// atomics, and finally adds the tile to d_table with plain loads and stores (no
+// other workgroup owns those rows).
+//
+// A pre-pass records, per (query, level), a 32-bit mask of the tiles the query's
+// corners touch (tile t of a level with P tiles sets bit t*32/P).  A tile
+// workgroup reads the masks of its level, compacts the queries whose bit is set
+// into an LDS queue and runs the corner work on full wavefronts of those queries
+// only.  With pi_1 = 1 the two x-corners of a hashed level share a tile, so a
+// query touches at most 8 of a hashed level's tiles.
 // PAIR: each query also subtracts the same gradient at the corners of x + eps (the
 // second term of Eq. 11).
+
+template <bool PAIR>
+__global__ __launch_bounds__(kEncodeBlock) void k_tile_mask(DevGrid g, TileMap tm, const float4* __restrict__ xyzt,
+                                                            const float4* __restrict__ eps, int n,
+                                                            uint32_t* __restrict__ mask) {
+    const int l = blockIdx.y;
+    const int q = blockIdx.x * kEncodeBlock + threadIdx.x;
+    if (q >= n) return;
+    const float4 x = xyzt[q];
+    uint32_t m = corner_tile_mask(g, tm, l, x);
+    if constexpr (PAIR) {
+        const float4 e = eps[q];
+        const float4 xp = make_float4(__fadd_rn(x.x, e.x), __fadd_rn(x.y, e.y), __fadd_rn(x.z, e.z),
+                                      __fadd_rn(x.w, e.w));
+        m |= corner_tile_mask(g, tm, l, xp);
+    }
+    mask[(int64_t)l * n + q] = m;
+}
+
 // 1024 threads share each tile: the 128 KiB of LDS allows one workgroup per CU, and
 // sixteen wavefronts (four per SIMD) keep the query loads in flight.
 constexpr int kScatterBlock = 1024;
+constexpr int kQueueCap = 2 * kScatterBlock;
+
+template <typename G, int F, bool PAIR>
+__device__ __forceinline__ void tile_query(const DevGrid& g, int l, const float4* __restrict__ xyzt,
+                                           const float4* __restrict__ eps, const G* __restrict__ src,
+                                           int64_t lstride, int64_t qstride, G scale, int q, uint32_t base,
+                                           uint32_t cnt, G* tile) {
+    const G* gp = src + (int64_t)l * lstride + (int64_t)q * qstride;
+    G gv[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) gv[f] = gp[f] * scale;
+    const float4 x = xyzt[q];
+    tile_contrib<G, F>(g, l, x, gv, base, cnt, tile);
+    if constexpr (PAIR) {
+        const float4 e = eps[q];
+        const float4 xp = make_float4(__fadd_rn(x.x, e.x), __fadd_rn(x.y, e.y), __fadd_rn(x.z, e.z),
+                                      __fadd_rn(x.w, e.w));
+        G gm[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) gm[f] = -gv[f];
+        tile_contrib<G, F>(g, l, xp, gm, base, cnt, tile);
+    }
+}
 
 template <typename G, int F, bool PAIR>
 __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, TileMap tm, const float4* __restrict__ xyzt,
                                                                 const float4* __restrict__ eps, int n,
+                                                                const uint32_t* __restrict__ mask,
                                                                 const G* __restrict__ src, int64_t lstride,
                                                                 int64_t qstride, G scale, G* __restrict__ d_table) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int queue[kQueueCap];
+    __shared__ int qcount;
     G* tile = reinterpret_cast<G*>(smem);
     int l = 0;
     while (l + 1 < g.L && (int)blockIdx.x >= tm.tile_start[l + 1]) ++l;
-    const uint32_t first = (uint32_t)((int)blockIdx.x - tm.tile_start[l]) * (uint32_t)tm.rows_per_tile;
+    const uint32_t t_in_level = (uint32_t)((int)blockIdx.x - tm.tile_start[l]);
+    const uint32_t first = t_in_level * (uint32_t)tm.rows_per_tile;
     const uint32_t base = g.off[l] + first;
     const uint32_t cnt = min((uint32_t)tm.rows_per_tile, (uint32_t)tm.level_rows[l] - first);
+    const uint32_t bit = tile_bit(tm, l, first);
     for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) tile[i] = G(0);
-    __syncthreads();
-    for (int q = threadIdx.x; q < n; q += kScatterBlock) {
-        const G* gp = src + (int64_t)l * lstride + (int64_t)q * qstride;
-        G gv[F];
-#pragma unroll
-        for (int f = 0; f < F; ++f) gv[f] = gp[f] * scale;
-        const float4 x = xyzt[q];
-        tile_contrib<G, F>(g, l, x, gv, base, cnt, tile);
-        if constexpr (PAIR) {
-            const float4 e = eps[q];
-            const float4 xp = make_float4(__fadd_rn(x.x, e.x), __fadd_rn(x.y, e.y), __fadd_rn(x.z, e.z),
-                                          __fadd_rn(x.w, e.w));
-            G gm[F];
-#pragma unroll
-            for (int f = 0; f < F; ++f) gm[f] = -gv[f];
-            tile_contrib<G, F>(g, l, xp, gm, base, cnt, tile);
-        }
-    }
-    __syncthreads();
+    masked_queue_loop<kScatterBlock>(n, mask + (int64_t)l * n, bit, queue, &qcount, [&](int q) {
+        tile_query<G, F, PAIR>(g, l, xyzt, eps, src, lstride, qstride, scale, q, base, cnt, tile);
+    });
     G* out = d_table + (size_t)base * F;
     for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) {
         const G v = tile[i];
@@ -164,41 +201,51 @@ TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gb
     return tm;
 }
 
+size_t scatter_mask_bytes(int n, int L) { return (size_t)n * L * sizeof(uint32_t); }
+
 template <typename G, int F, bool PAIR>
 static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt, const float* eps, int n,
-                          const void* src, int64_t ls, int64_t qs, double scale, void* d_table, hipStream_t s) {
+                          const uint32_t* mask, const void* src, int64_t ls, int64_t qs, double scale, void* d_table,
+                          hipStream_t s) {
     auto kern = k_scatter_tiled<G, F, PAIR>;
     const size_t lds = (size_t)tm.rows_per_tile * F * sizeof(G);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(tm.tile_start[g.L]), dim3(kScatterBlock), lds, s, g, tm,
-                       reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n,
+                       reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n, mask,
                        static_cast<const G*>(src), ls, qs, (G)scale, static_cast<G*>(d_table));
     return hipGetLastError();
 }
 
 template <typename G, bool PAIR>
 static hipError_t tiled_g(const DevGrid& g, const int64_t* level_rows, const float* xyzt, const float* eps, int n,
-                          const void* src, int64_t ls, int64_t qs, double scale, void* d_table, hipStream_t s) {
+                          const void* src, int64_t ls, int64_t qs, double scale, void* d_table, void* mask_ws,
+                          hipStream_t s) {
     const TileMap tm = make_tile_map(g, level_rows, g.F, (int)sizeof(G));
+    uint32_t* mask = static_cast<uint32_t*>(mask_ws);
+    hipLaunchKernelGGL(k_tile_mask<PAIR>, dim3((unsigned)((n + kEncodeBlock - 1) / kEncodeBlock), (unsigned)g.L),
+                       dim3(kEncodeBlock), 0, s, g, tm, reinterpret_cast<const float4*>(xyzt),
+                       reinterpret_cast<const float4*>(eps), n, mask);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     switch (g.F) {
-        case 1: return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, src, ls, qs, scale, d_table, s);
-        case 2: return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, src, ls, qs, scale, d_table, s);
-        case 4: return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, src, ls, qs, scale, d_table, s);
-        case 8: return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, src, ls, qs, scale, d_table, s);
+        case 1: return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, s);
+        case 2: return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, s);
+        case 4: return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, s);
+        case 8: return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d_dtype grad_dt, const float* xyzt,
                                 const float* eps, int n, const void* src, int64_t ls, int64_t qs, double scale,
-                                void* d_table, hipStream_t s) {
+                                void* d_table, void* mask_ws, hipStream_t s) {
     if (grad_dt == H4D_F64) {
-        return eps ? tiled_g<double, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, s)
-                   : tiled_g<double, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, s);
+        return eps ? tiled_g<double, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, s)
+                   : tiled_g<double, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, s);
     }
-    return eps ? tiled_g<float, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, s)
-               : tiled_g<float, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, s);
+    return eps ? tiled_g<float, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, s)
+               : tiled_g<float, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, s);
 }
 
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w, hipStream_t s) {

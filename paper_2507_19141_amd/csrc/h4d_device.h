@@ -187,4 +187,57 @@ __device__ __forceinline__ void tile_contrib(const DevGrid& g, int l, float4 x, 
     }
 }
 
+// Bit of the tile holding level-relative row rel_row: tile t of a level with P
+// tiles sets bit t*32/P of a query's mask.
+__device__ __forceinline__ uint32_t tile_bit(const TileMap& tm, int l, uint32_t rel_row) {
+    const uint32_t t = rel_row / (uint32_t)tm.rows_per_tile;
+    const uint32_t P = (uint32_t)(tm.tile_start[l + 1] - tm.tile_start[l]);
+    return 1u << ((t * 32u) / P);
+}
+
+__device__ __forceinline__ uint32_t corner_tile_mask(const DevGrid& g, const TileMap& tm, int l, float4 x) {
+    const Cell c = level_cell(g, l, x);
+    uint32_t row[16];
+    level_rows(g, l, c, row);
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) m |= tile_bit(tm, l, row[k] - g.off[l]);
+    return m;
+}
+
+// Run work(q) for every q < n whose tile mask lmask[q] has `bit` set, on full
+// batches of BLOCK threads: each BLOCK-query chunk is tested, the hits are
+// compacted into an LDS queue (capacity 2 BLOCK), and whenever BLOCK of them are
+// queued every thread handles one.  All threads of the workgroup must call it.
+template <int BLOCK, typename Work>
+__device__ __forceinline__ void masked_queue_loop(int n, const uint32_t* __restrict__ lmask, uint32_t bit, int* queue,
+                                                  int* qcount, Work work) {
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) *qcount = 0;
+    __syncthreads();
+    for (int q0 = 0; q0 < n; q0 += BLOCK) {
+        const int q = q0 + (int)threadIdx.x;
+        const bool hit = q < n && (lmask[q] & bit);
+        const uint64_t bal = __ballot(hit);
+        int wbase = 0;
+        if (lane == 0 && bal) wbase = atomicAdd(qcount, (int)__popcll(bal));
+        wbase = __shfl(wbase, 0, 64);
+        if (hit) queue[wbase + __popcll(bal & ((1ull << lane) - 1ull))] = q;
+        __syncthreads();
+        const int qn = *qcount;
+        if (qn >= BLOCK) {
+            work(queue[threadIdx.x]);
+            __syncthreads();
+            const int rest = qn - BLOCK;
+            const int moved = (int)threadIdx.x < rest ? queue[BLOCK + threadIdx.x] : 0;
+            __syncthreads();
+            if ((int)threadIdx.x < rest) queue[threadIdx.x] = moved;
+            if (threadIdx.x == 0) *qcount = rest;
+        }
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < *qcount) work(queue[threadIdx.x]);
+    __syncthreads();
+}
+
 }  // namespace h4d

@@ -44,9 +44,11 @@ struct TileMap {
     int32_t level_rows[H4D_MAX_LEVELS];
 };
 TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes);
+// Workspace of the scatter: one 32-bit tile mask per (query, level).
+size_t scatter_mask_bytes(int n, int L);
 hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d_dtype grad_dt, const float* xyzt,
                                 const float* eps, int n, const void* src, int64_t lstride, int64_t qstride,
-                                double scale, void* d_table, hipStream_t s);
+                                double scale, void* d_table, void* mask_ws, hipStream_t s);
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w,
                                  hipStream_t s);
 

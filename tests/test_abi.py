@@ -120,7 +120,10 @@ def test_entry_points_validate_without_launching():
     assert lib.hash4d_encode(gp, 0, fake, fake, 5, 2, fake, None) == -1                # unknown layout
     assert lib.hash4d_encode(gp, 0, fake, fake, -1, 0, fake, None) == -1               # negative n
     assert lib.hash4d_encode(gp, 0, fake, fake, 1 << 31, 0, fake, None) == -1          # n too large
-    assert lib.hash4d_encode_backward(gp, 1, fake, 5, 0, fake, 1.0, fake, None) == -1  # grads must be F32/F64
+    assert lib.hash4d_encode_backward(gp, 1, fake, 5, 0, fake, 1.0, fake, fake, 1 << 20, None) == -1  # F32/F64 grads
+    assert lib.hash4d_encode_backward(gp, 0, fake, 5, 0, fake, 1.0, fake, fake, 4, None) == -1        # small workspace
+    assert "workspace" in _lib.last_error()
+    assert _lib.hash4d_encode_backward_workspace_bytes(g, 1000) == 1000 * 4 * 4
     assert lib.hash4d_corner_indices(gp, fake, 5, None, None, None) == -1
     assert lib.hash4d_encode(None, 0, fake, fake, 5, 0, fake, None) == -1
     m = _lib.mlp_shape(32)

@@ -90,8 +90,10 @@ def run_backward(lg, dt, x, gf, E, scale=1.0):
     n = x.shape[0]
     tdt = torch.float64 if dt == _lib.F64 else torch.float32
     d_table = torch.zeros((E, lg.F), dtype=tdt, device="cuda")
+    wb = _lib.hash4d_encode_backward_workspace_bytes(lg, n)
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
     _lib.hash4d_encode_backward(lg, dt, dev(x), n, dev(gf.astype(np.float64 if dt == _lib.F64 else np.float32)),
-                                scale, d_table)
+                                scale, d_table, ws, wb)
     return host(d_table)
 
 
@@ -198,7 +200,9 @@ def test_encode_backward_accumulates():
     og, lg, x, _, rng = encoder_case(synth.ENCODER_SMALL, 1000, 9, edges=False)
     gf = synth.upstream(1000, og.L * og.F, rng)
     d = torch.ones((og.E, og.F), dtype=torch.float32, device="cuda")
-    _lib.hash4d_encode_backward(lg, _lib.F32, dev(x), 1000, dev(gf), 1.0, d)
+    wb = _lib.hash4d_encode_backward_workspace_bytes(lg, 1000)
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    _lib.hash4d_encode_backward(lg, _lib.F32, dev(x), 1000, dev(gf), 1.0, d, ws, wb)
     ref = 1.0 + O.encode_backward(x, gf, og)
     scaled_close(host(d), ref, 1.0 + O.encode_backward(x, np.abs(gf), og), RTOL_GRAD, "d_table +=")
 
