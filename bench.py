@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-probes", action="store_true", help="skip the roofline probes")
     ap.add_argument("--no-batched", action="store_true", help="skip the multi-scene form")
+    ap.add_argument("--counters", action="store_true",
+                    help="a few FP32 steps plus one 256 MiB copy kernel (the calibration reference of the "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE passes); prints the step kernels' names")
     ap.add_argument("--probe-sweep", action="store_true",
                     help="only run the gather / atomic probes over several footprints and print them")
     ap.add_argument("--cpu-sample", type=int, default=40000, help="queries the CPU oracle is timed on")
@@ -229,6 +232,15 @@ def probe_sweep(torch, _lib, E, n_loads, reps=5):
         torch.cuda.synchronize()
         out[f"scatter_sum_mode{mode}"] = float(buf.double().sum())
     out["scatter_sum_expected"] = 2.0 * n_loads
+    # LDS atomics, 128 KiB tile per 1024-thread workgroup, 512 workgroups
+    sink = torch.zeros(1, device="cuda")
+    out["lds_atomic"] = []
+    for active in (64, 8):
+        per = 256
+        t = timed(lambda: _lib.h4d_probe_lds_atomic(512, per, active, 3, sink))
+        ops = 512 * 1024 * per * active / 64
+        out["lds_atomic"].append({"active_lanes": active, "ms": t * 1e3, "G_ops_per_s": ops / t / 1e9,
+                                  "G_instr_per_s": 512 * 16 * per / t / 1e9})
     return out
 
 
@@ -360,6 +372,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     _lib.load()
+    if args.counters:
+        fp = Path(torch, _lib, synth, "fp32")
+        fp.run(max(1, args.steps), 1)
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 4, device="cuda")
+        dst = torch.empty_like(src)
+        _lib.h4d_probe_copy(src, dst, nbytes)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_run": {"steps": args.steps + 1, "copy_bytes": nbytes,
+                                           "copy_kernel": "k_probe_copy"}}), flush=True)
+        return
     if args.probe_sweep:
         w = synth.PAPER_SCENE
         E = _lib.h4d_grid_init(w.L, w.F, _lib.h4d_grid_schedule(w.L, *w.space),

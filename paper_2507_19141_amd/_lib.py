@@ -111,6 +111,7 @@ SIGNATURES = {
     "h4d_probe_gather": (_I32, [_P, _I64, _I32, _I64, ctypes.c_uint32, _P, _P]),
     "h4d_probe_scatter": (_I32, [_P, _I64, _I64, ctypes.c_uint32, _I32, _P]),
     "h4d_probe_copy": (_I32, [_P, _P, _I64, _P]),
+    "h4d_probe_lds_atomic": (_I32, [_I32, _I32, _I32, ctypes.c_uint32, _P, _P]),
 }
 
 _lib = None
@@ -343,6 +344,11 @@ def h4d_probe_scatter(table, rows: int, n_updates: int, seed: int, mode: int = 0
 
 def h4d_probe_copy(src, dst, nbytes: int, stream=None) -> None:
     _check("h4d_probe_copy", load().h4d_probe_copy(ptr(src), ptr(dst), nbytes, stream_handle(stream)))
+
+
+def h4d_probe_lds_atomic(blocks: int, per_thread: int, active: int, seed: int, sink, stream=None) -> None:
+    _check("h4d_probe_lds_atomic", load().h4d_probe_lds_atomic(blocks, per_thread, active, seed, ptr(sink),
+                                                               stream_handle(stream)))
 
 
 def hip_runtimes_loaded() -> list:

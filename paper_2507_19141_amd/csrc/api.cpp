@@ -366,6 +366,16 @@ h4d_status h4d_probe_copy(const void* src, void* dst, int64_t bytes, void* strea
     return hip_status(launch_probe_copy(src, dst, bytes, (hipStream_t)stream), "h4d_probe_copy");
 }
 
+h4d_status h4d_probe_lds_atomic(int32_t blocks, int32_t per_thread, int32_t active, uint32_t seed, float* sink,
+                                void* stream) {
+    g_last_error.clear();
+    if (blocks < 1 || blocks > 1 << 20 || per_thread < 0 || per_thread > 1 << 16 || active < 1 || active > 64)
+        return fail(H4D_EINVAL, "blocks 1..2^20, per_thread 0..65536, active 1..64");
+    if (!sink) return fail(H4D_EINVAL, "sink is NULL");
+    return hip_status(launch_probe_lds_atomic(blocks, per_thread, active, seed, sink, (hipStream_t)stream),
+                      "h4d_probe_lds_atomic");
+}
+
 size_t deform_mlp_workspace_bytes(const h4d_mlp* m, h4d_dtype dt, int64_t n) {
     if (check_mlp(m, dt) != H4D_OK || n < 0 || n > kMaxN) return 0;
     return mlp_workspace_bytes(dt, m->in, m->out, (int)n);

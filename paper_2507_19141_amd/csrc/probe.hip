@@ -106,3 +106,40 @@ hipError_t launch_probe_copy(const void* src, void* dst, int64_t bytes, hipStrea
 }
 
 }  // namespace h4d
+
+namespace h4d {
+
+// LDS atomics: each workgroup (1024 threads) owns a 128 KiB FP32 tile and issues
+// `per_thread` ds_add_f32 per thread to pseudo-random words of it; `active` of
+// every 64 lanes take part (the rest sit out each instruction), like the table
+// scatter where only the lanes whose corner falls in the tile add.
+__global__ __launch_bounds__(1024) void k_probe_lds_atomic(int per_thread, int active, uint32_t seed,
+                                                           float* __restrict__ sink) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* tile = reinterpret_cast<float*>(smem);
+    constexpr int kWords = 32768;
+    for (int i = threadIdx.x; i < kWords; i += 1024) tile[i] = 0.f;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t id = blockIdx.x * 1024u + threadIdx.x;
+    if ((int)lane < active) {
+        for (int k = 0; k < per_thread; ++k) {
+            const uint32_t w = mix32(id * 977u + (uint32_t)k * 0x9e3779b9u + seed) & (kWords - 1);
+            atomicAdd(tile + w, 1.0f);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && tile[seed & (kWords - 1)] == -1.0f) sink[0] = 1.f;  // keeps the adds alive
+}
+
+hipError_t launch_probe_lds_atomic(int blocks, int per_thread, int active, uint32_t seed, float* sink,
+                                   hipStream_t s) {
+    const size_t lds = 128 * 1024;
+    hipError_t e = hipFuncSetAttribute((const void*)k_probe_lds_atomic, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_probe_lds_atomic, dim3(blocks), dim3(1024), lds, s, per_thread, active, seed, sink);
+    return hipGetLastError();
+}
+
+}  // namespace h4d
