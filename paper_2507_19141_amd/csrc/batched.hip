@@ -123,15 +123,15 @@ __global__ __launch_bounds__(kBatchScatterBlock) void k_bscatter(const BSeg* __r
                                                                  const BTile* __restrict__ tiles, float scale) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int queue[2 * kBatchScatterBlock];
-    __shared__ int qcount;
     float* tile = reinterpret_cast<float*>(smem);
     const BTile tl = tiles[blockIdx.x];
     const DevGrid& g = grids[tl.scene];
     const int l = tl.level;
     for (uint32_t i = threadIdx.x; i < tl.cnt * F; i += kBatchScatterBlock) tile[i] = 0.f;
+    __syncthreads();
     for (int sgi = tl.seg0; sgi < tl.seg0 + tl.nseg; ++sgi) {
         const BSeg sg = segs[sgi];
-        masked_queue_loop<kBatchScatterBlock>(sg.n, sg.mask + (int64_t)l * sg.n, tl.bit, queue, &qcount, [&](int q) {
+        masked_queue_loop<kBatchScatterBlock>(sg.n, sg.mask + (int64_t)l * sg.n, tl.bit, queue, [&](int q) {
             const float* gp = sg.d_feat + ((int64_t)l * sg.n + q) * F;
             float gv[F];
 #pragma unroll
@@ -141,6 +141,7 @@ __global__ __launch_bounds__(kBatchScatterBlock) void k_bscatter(const BSeg* __r
             tile_contrib<float, F>(g, l, x, gv, tl.base, tl.cnt, tile);
         });
     }
+    __syncthreads();
     float* out = segs[tl.seg0].d_table + (size_t)tl.base * F;
     for (uint32_t i = threadIdx.x; i < tl.cnt * F; i += kBatchScatterBlock) {
         const float v = tile[i];

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kEncodeBlock) void k_tile_mask(DevGrid g, TileMap t
 // 1024 threads share each tile: the 128 KiB of LDS allows one workgroup per CU, and
 // sixteen wavefronts (four per SIMD) keep the query loads in flight.
 constexpr int kScatterBlock = 1024;
-constexpr int kQueueCap = 2 * kScatterBlock;
+constexpr int kQueueCap = 2 * kScatterBlock;  // 128 entries per wavefront
 
 template <typename G, int F, bool PAIR>
 __device__ __forceinline__ void tile_query(const DevGrid& g, int l, const float4* __restrict__ xyzt,
@@ -117,7 +117,6 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
                                                                 int64_t qstride, G scale, G* __restrict__ d_table) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int queue[kQueueCap];
-    __shared__ int qcount;
     G* tile = reinterpret_cast<G*>(smem);
     int l = 0;
     while (l + 1 < g.L && (int)blockIdx.x >= tm.tile_start[l + 1]) ++l;
@@ -127,9 +126,11 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
     const uint32_t cnt = min((uint32_t)tm.rows_per_tile, (uint32_t)tm.level_rows[l] - first);
     const uint32_t bit = tile_bit(tm, l, first);
     for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) tile[i] = G(0);
-    masked_queue_loop<kScatterBlock>(n, mask + (int64_t)l * n, bit, queue, &qcount, [&](int q) {
+    __syncthreads();
+    masked_queue_loop<kScatterBlock>(n, mask + (int64_t)l * n, bit, queue, [&](int q) {
         tile_query<G, F, PAIR>(g, l, xyzt, eps, src, lstride, qstride, scale, q, base, cnt, tile);
     });
+    __syncthreads();
     G* out = d_table + (size_t)base * F;
     for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) {
         const G v = tile[i];

@@ -205,39 +205,48 @@ __device__ __forceinline__ uint32_t corner_tile_mask(const DevGrid& g, const Til
     return m;
 }
 
-// Run work(q) for every q < n whose tile mask lmask[q] has `bit` set, on full
-// batches of BLOCK threads: each BLOCK-query chunk is tested, the hits are
-// compacted into an LDS queue (capacity 2 BLOCK), and whenever BLOCK of them are
-// queued every thread handles one.  All threads of the workgroup must call it.
+// Run work(q) for every q < n whose tile mask lmask[q] has `bit` set.  Each
+// wavefront scans its own interleaved slice of the queries (64 masks per step,
+// the next step's masks already in flight), compacts the hits into a private LDS
+// queue of 128 entries and runs work() on full 64-lane batches; no workgroup-wide
+// barrier is involved, so the wavefronts of a workgroup overlap freely.
+// Orders one wavefront's LDS queue writes before its reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int BLOCK, typename Work>
-__device__ __forceinline__ void masked_queue_loop(int n, const uint32_t* __restrict__ lmask, uint32_t bit, int* queue,
-                                                  int* qcount, Work work) {
+__device__ __forceinline__ void masked_queue_loop(int n, const uint32_t* __restrict__ lmask, uint32_t bit,
+                                                  int* wqueue, Work work) {
+    static_assert(BLOCK % 64 == 0, "whole wavefronts");
     const int lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) *qcount = 0;
-    __syncthreads();
-    for (int q0 = 0; q0 < n; q0 += BLOCK) {
-        const int q = q0 + (int)threadIdx.x;
-        const bool hit = q < n && (lmask[q] & bit);
+    const int wave = threadIdx.x >> 6;
+    int* queue = wqueue + wave * 128;
+    int qn = 0;
+    int q = wave * 64 + lane;
+    uint32_t m = q < n ? lmask[q] : 0u;
+    for (int q0 = wave * 64; q0 < n; q0 += BLOCK) {
+        const int qn_next = q + BLOCK;
+        const uint32_t m_next = qn_next < n ? lmask[qn_next] : 0u;
+        const bool hit = (m & bit) != 0u;
         const uint64_t bal = __ballot(hit);
-        int wbase = 0;
-        if (lane == 0 && bal) wbase = atomicAdd(qcount, (int)__popcll(bal));
-        wbase = __shfl(wbase, 0, 64);
-        if (hit) queue[wbase + __popcll(bal & ((1ull << lane) - 1ull))] = q;
-        __syncthreads();
-        const int qn = *qcount;
-        if (qn >= BLOCK) {
-            work(queue[threadIdx.x]);
-            __syncthreads();
-            const int rest = qn - BLOCK;
-            const int moved = (int)threadIdx.x < rest ? queue[BLOCK + threadIdx.x] : 0;
-            __syncthreads();
-            if ((int)threadIdx.x < rest) queue[threadIdx.x] = moved;
-            if (threadIdx.x == 0) *qcount = rest;
+        if (hit) queue[qn + __popcll(bal & ((1ull << lane) - 1ull))] = q;
+        qn += (int)__popcll(bal);
+        wave_sync();
+        if (qn >= 64) {
+            work(queue[lane]);
+            const int rest = qn - 64;
+            const int moved = lane < rest ? queue[64 + lane] : 0;
+            wave_sync();
+            if (lane < rest) queue[lane] = moved;
+            wave_sync();
+            qn = rest;
         }
-        __syncthreads();
+        q = qn_next;
+        m = m_next;
     }
-    if ((int)threadIdx.x < *qcount) work(queue[threadIdx.x]);
-    __syncthreads();
+    if (lane < qn) work(queue[lane]);
 }
 
 }  // namespace h4d
