@@ -235,12 +235,13 @@ def probe_sweep(torch, _lib, E, n_loads, reps=5):
     # LDS atomics, 128 KiB tile per 1024-thread workgroup, 512 workgroups
     sink = torch.zeros(1, device="cuda")
     out["lds_atomic"] = []
-    for active in (64, 8):
-        per = 256
-        t = timed(lambda: _lib.h4d_probe_lds_atomic(512, per, active, 3, sink))
-        ops = 512 * 1024 * per * active / 64
-        out["lds_atomic"].append({"active_lanes": active, "ms": t * 1e3, "G_ops_per_s": ops / t / 1e9,
-                                  "G_instr_per_s": 512 * 16 * per / t / 1e9})
+    for mode, kind in ((0, "ds_add_f32"), (1, "ds_add_u32"), (2, "f32 compare-and-swap")):
+        for active in (64, 8):
+            per = 256
+            t = timed(lambda: _lib.h4d_probe_lds_atomic(512, per, active, 3, mode, sink))
+            ops = 512 * 1024 * per * active / 64
+            out["lds_atomic"].append({"kind": kind, "active_lanes": active, "ms": t * 1e3,
+                                      "G_ops_per_s": ops / t / 1e9, "G_instr_per_s": 512 * 16 * per / t / 1e9})
     return out
 
 

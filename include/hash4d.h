@@ -332,10 +332,13 @@ h4d_status h4d_probe_gather(const void* table, int64_t rows, int32_t row_bytes, 
 h4d_status h4d_probe_scatter(float* table, int64_t rows, int64_t n_updates, uint32_t seed, int32_t mode,
                              void* stream);
 h4d_status h4d_probe_copy(const void* src, void* dst, int64_t bytes, void* stream);
-/* lds atomic: `blocks` workgroups of 1024 threads, each with a 128 KiB FP32 LDS tile;
- *          `active` of every 64 lanes issue `per_thread` ds_add_f32 to random words. */
-h4d_status h4d_probe_lds_atomic(int32_t blocks, int32_t per_thread, int32_t active, uint32_t seed, float* sink,
-                                void* stream);
+/* lds atomic: `blocks` workgroups of 1024 threads, each with a 128 KiB LDS tile;
+ *          `active` of every 64 lanes each add to `per_thread` random words.
+ *          mode 0: FP32 atomic add (ds_add_f32); mode 1: 32-bit integer atomic add
+ *          (ds_add_u32); mode 2: FP32 add by compare-and-swap loop (the library's
+ *          tile accumulation).  Returns H4D_EINVAL for any other mode. */
+h4d_status h4d_probe_lds_atomic(int32_t blocks, int32_t per_thread, int32_t active, uint32_t seed, int32_t mode,
+                                float* sink, void* stream);
 
 #ifdef __cplusplus
 }

@@ -111,7 +111,7 @@ SIGNATURES = {
     "h4d_probe_gather": (_I32, [_P, _I64, _I32, _I64, ctypes.c_uint32, _P, _P]),
     "h4d_probe_scatter": (_I32, [_P, _I64, _I64, ctypes.c_uint32, _I32, _P]),
     "h4d_probe_copy": (_I32, [_P, _P, _I64, _P]),
-    "h4d_probe_lds_atomic": (_I32, [_I32, _I32, _I32, ctypes.c_uint32, _P, _P]),
+    "h4d_probe_lds_atomic": (_I32, [_I32, _I32, _I32, ctypes.c_uint32, _I32, _P, _P]),
 }
 
 _lib = None
@@ -346,8 +346,8 @@ def h4d_probe_copy(src, dst, nbytes: int, stream=None) -> None:
     _check("h4d_probe_copy", load().h4d_probe_copy(ptr(src), ptr(dst), nbytes, stream_handle(stream)))
 
 
-def h4d_probe_lds_atomic(blocks: int, per_thread: int, active: int, seed: int, sink, stream=None) -> None:
-    _check("h4d_probe_lds_atomic", load().h4d_probe_lds_atomic(blocks, per_thread, active, seed, ptr(sink),
+def h4d_probe_lds_atomic(blocks: int, per_thread: int, active: int, seed: int, mode: int, sink, stream=None) -> None:
+    _check("h4d_probe_lds_atomic", load().h4d_probe_lds_atomic(blocks, per_thread, active, seed, mode, ptr(sink),
                                                                stream_handle(stream)))
 
 

@@ -366,13 +366,14 @@ h4d_status h4d_probe_copy(const void* src, void* dst, int64_t bytes, void* strea
     return hip_status(launch_probe_copy(src, dst, bytes, (hipStream_t)stream), "h4d_probe_copy");
 }
 
-h4d_status h4d_probe_lds_atomic(int32_t blocks, int32_t per_thread, int32_t active, uint32_t seed, float* sink,
-                                void* stream) {
+h4d_status h4d_probe_lds_atomic(int32_t blocks, int32_t per_thread, int32_t active, uint32_t seed, int32_t mode,
+                                float* sink, void* stream) {
     g_last_error.clear();
     if (blocks < 1 || blocks > 1 << 20 || per_thread < 0 || per_thread > 1 << 16 || active < 1 || active > 64)
         return fail(H4D_EINVAL, "blocks 1..2^20, per_thread 0..65536, active 1..64");
+    if (mode < 0 || mode > 2) return fail(H4D_EINVAL, "mode must be 0, 1 or 2");
     if (!sink) return fail(H4D_EINVAL, "sink is NULL");
-    return hip_status(launch_probe_lds_atomic(blocks, per_thread, active, seed, sink, (hipStream_t)stream),
+    return hip_status(launch_probe_lds_atomic(blocks, per_thread, active, seed, mode, sink, (hipStream_t)stream),
                       "h4d_probe_lds_atomic");
 }
 

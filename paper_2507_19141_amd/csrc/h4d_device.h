@@ -164,6 +164,23 @@ template <> struct AccOf<double> { using type = double; };
 __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
+// Add v to an FP32 word of LDS.  gfx950 runs ds_add_f32 at about one active lane
+// per three clocks per CU, while its integer LDS atomics run near full rate, so the
+// add is a compare-and-swap loop on the bit pattern: read, add in FP32, swap in if
+// the word is unchanged, else retry with the value the swap returned.  Each add
+// still rounds once; the order of the adds is unspecified, as with any atomic.
+__device__ __forceinline__ void lds_add(float* p, float v) {
+    unsigned int* u = reinterpret_cast<unsigned int*>(p);
+    unsigned int seen = *reinterpret_cast<volatile unsigned int*>(u);
+    while (true) {
+        const unsigned int want = __float_as_uint(__uint_as_float(seen) + v);
+        const unsigned int prev = atomicCAS(u, seen, want);
+        if (prev == seen) break;
+        seen = prev;
+    }
+}
+__device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
+
 // Add w_c gv at the corners of x that fall in table rows [base, base + cnt) to an
 // LDS tile (row r at tile[(r - base) F]).
 template <typename G, int F>
@@ -182,7 +199,7 @@ __device__ __forceinline__ void tile_contrib(const DevGrid& g, int l, float4 x, 
         if (r < cnt) {
             const G w = ((wx[k & 1] * wy[(k >> 1) & 1]) * wz[(k >> 2) & 1]) * wt[k >> 3];
 #pragma unroll
-            for (int f = 0; f < F; ++f) atomicAdd(tile + r * F + f, w * gv[f]);
+            for (int f = 0; f < F; ++f) lds_add(tile + r * F + f, w * gv[f]);
         }
     }
 }

@@ -121,7 +121,7 @@ hipError_t launch_probe_gather(const void* table, uint32_t rows, int row_bytes, 
 hipError_t launch_probe_scatter(float* table, uint32_t rows, int64_t n_updates, uint32_t seed, int mode,
                                 hipStream_t s);
 hipError_t launch_probe_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
-hipError_t launch_probe_lds_atomic(int blocks, int per_thread, int active, uint32_t seed, float* sink,
+hipError_t launch_probe_lds_atomic(int blocks, int per_thread, int active, uint32_t seed, int mode, float* sink,
                                    hipStream_t s);
 
 }  // namespace h4d

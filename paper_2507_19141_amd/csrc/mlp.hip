@@ -610,50 +610,57 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int 
         for (int idx = 0; idx < Sh::NO; ++idx) sb3[idx] += __shfl_xor(sb3[idx], s, 64);
     }
 
-    // Emit this wavefront's partial gradient: into the block accumulator (LDS
-    // atomics) for FP32/BF16, straight into its own workspace row for FP64.
-    G* dst = kLds ? wacc : partial + (size_t)(blockIdx.x * kWaves + (threadIdx.x >> 6)) * po.P;
+    // Emit the wavefront partial gradients.  FP32/BF16: the wavefronts add theirs to
+    // the block accumulator in LDS one after another (plain read-modify-write; every
+    // lane of an emit touches a different parameter), so the block sum has a fixed
+    // order.  FP64: each wavefront writes its own workspace row.
+    const int wave = threadIdx.x >> 6;
+    G* dst = kLds ? wacc : partial + (size_t)(blockIdx.x * kWaves + wave) * po.P;
     auto emit = [&](int p, G v) {
-        if constexpr (kLds) atomicAdd(dst + p, v);
+        if constexpr (kLds) dst[p] += v;
         else dst[p] = v;
     };
+    for (int round = 0; round < (kLds ? kWaves : 1); ++round) {
+        if (!kLds || wave == round) {
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+            for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int o = 4 * kb + r;
-            if (o < out) emit(po.W3 + o * HID + 16 * nt + j, (G)Pol::get(w3[nt], r));
-        }
+                for (int r = 0; r < 4; ++r) {
+                    const int o = 4 * kb + r;
+                    if (o < out) emit(po.W3 + o * HID + 16 * nt + j, (G)Pol::get(w3[nt], r));
+                }
 #pragma unroll
-    for (int mo = 0; mo < 4; ++mo)
+            for (int mo = 0; mo < 4; ++mo)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
+                for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                emit(po.W2 + (16 * mo + 4 * kb + r) * HID + 16 * nt + j, (G)Pol::get(w2[mo][nt], r));
+                    for (int r = 0; r < 4; ++r)
+                        emit(po.W2 + (16 * mo + 4 * kb + r) * HID + 16 * nt + j, (G)Pol::get(w2[mo][nt], r));
 #pragma unroll
-    for (int mo = 0; mo < 4; ++mo)
+            for (int mo = 0; mo < 4; ++mo)
 #pragma unroll
-        for (int nf = 0; nf < Sh::MF; ++nf)
+                for (int nf = 0; nf < Sh::MF; ++nf)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int f = 16 * nf + j;
-                if (f < IN) emit(po.W1 + (16 * mo + 4 * kb + r) * IN + f, (G)Pol::get(w1[mo][nf], r));
+                    for (int r = 0; r < 4; ++r) {
+                        const int f = 16 * nf + j;
+                        if (f < IN) emit(po.W1 + (16 * mo + 4 * kb + r) * IN + f, (G)Pol::get(w1[mo][nf], r));
+                    }
+            if (j == 0) {
+#pragma unroll
+                for (int idx = 0; idx < 16; ++idx) {
+                    emit(po.b1 + hid(idx, kb), (G)sb1[idx]);
+                    emit(po.b2 + hid(idx, kb), (G)sb2[idx]);
+                }
+#pragma unroll
+                for (int idx = 0; idx < Sh::NO; ++idx) {
+                    const int o = kb * Sh::NO + idx;
+                    if (o < out) emit(po.b3 + o, (G)sb3[idx]);
+                }
             }
-    if (j == 0) {
-#pragma unroll
-        for (int idx = 0; idx < 16; ++idx) {
-            emit(po.b1 + hid(idx, kb), (G)sb1[idx]);
-            emit(po.b2 + hid(idx, kb), (G)sb2[idx]);
         }
-#pragma unroll
-        for (int idx = 0; idx < Sh::NO; ++idx) {
-            const int o = kb * Sh::NO + idx;
-            if (o < out) emit(po.b3 + o, (G)sb3[idx]);
-        }
+        if constexpr (kLds) __syncthreads();
     }
     if constexpr (kLds) {
-        __syncthreads();
         G* row = partial + (size_t)blockIdx.x * po.P;
         for (int t = threadIdx.x; t < po.P; t += blockDim.x) row[t] = wacc[t];
     }

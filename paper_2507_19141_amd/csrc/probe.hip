@@ -109,10 +109,12 @@ hipError_t launch_probe_copy(const void* src, void* dst, int64_t bytes, hipStrea
 
 namespace h4d {
 
-// LDS atomics: each workgroup (1024 threads) owns a 128 KiB FP32 tile and issues
-// `per_thread` ds_add_f32 per thread to pseudo-random words of it; `active` of
-// every 64 lanes take part (the rest sit out each instruction), like the table
-// scatter where only the lanes whose corner falls in the tile add.
+// LDS atomics: each workgroup (1024 threads) owns a 128 KiB tile and adds, per
+// thread, `per_thread` times to pseudo-random words of it; `active` of every 64
+// lanes take part (the rest sit out each instruction), like the table scatter
+// where only the lanes whose corner falls in the tile add.  MODE 0: ds_add_f32;
+// 1: ds_add_u32; 2: FP32 add by compare-and-swap (lds_add).
+template <int MODE>
 __global__ __launch_bounds__(1024) void k_probe_lds_atomic(int per_thread, int active, uint32_t seed,
                                                            float* __restrict__ sink) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -125,20 +127,25 @@ __global__ __launch_bounds__(1024) void k_probe_lds_atomic(int per_thread, int a
     if ((int)lane < active) {
         for (int k = 0; k < per_thread; ++k) {
             const uint32_t w = mix32(id * 977u + (uint32_t)k * 0x9e3779b9u + seed) & (kWords - 1);
-            atomicAdd(tile + w, 1.0f);
+            if constexpr (MODE == 0) atomicAdd(tile + w, 1.0f);
+            else if constexpr (MODE == 1) atomicAdd(reinterpret_cast<unsigned int*>(tile) + w, 1u);
+            else lds_add(tile + w, 1.0f);
         }
     }
     __syncthreads();
     if (threadIdx.x == 0 && tile[seed & (kWords - 1)] == -1.0f) sink[0] = 1.f;  // keeps the adds alive
 }
 
-hipError_t launch_probe_lds_atomic(int blocks, int per_thread, int active, uint32_t seed, float* sink,
+hipError_t launch_probe_lds_atomic(int blocks, int per_thread, int active, uint32_t seed, int mode, float* sink,
                                    hipStream_t s) {
     const size_t lds = 128 * 1024;
-    hipError_t e = hipFuncSetAttribute((const void*)k_probe_lds_atomic, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    const void* k = mode == 0 ? (const void*)k_probe_lds_atomic<0>
+                  : mode == 1 ? (const void*)k_probe_lds_atomic<1> : (const void*)k_probe_lds_atomic<2>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_probe_lds_atomic, dim3(blocks), dim3(1024), lds, s, per_thread, active, seed, sink);
+    if (mode == 0) hipLaunchKernelGGL(k_probe_lds_atomic<0>, dim3(blocks), dim3(1024), lds, s, per_thread, active, seed, sink);
+    else if (mode == 1) hipLaunchKernelGGL(k_probe_lds_atomic<1>, dim3(blocks), dim3(1024), lds, s, per_thread, active, seed, sink);
+    else hipLaunchKernelGGL(k_probe_lds_atomic<2>, dim3(blocks), dim3(1024), lds, s, per_thread, active, seed, sink);
     return hipGetLastError();
 }
 
