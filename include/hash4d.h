@@ -18,7 +18,8 @@
  *    clamped to [0, 1] (NaN counts as 0); normalising scene coordinates into the
  *    unit cube is the caller's job.
  *  - No entry point allocates device memory.  Scratch space, where needed, is a
- *    caller-provided workspace whose size a *_workspace_bytes call reports.
+ *    caller-provided workspace whose size a *_workspace_bytes call reports; it
+ *    must be 16-byte aligned (H4D_EINVAL otherwise).
  */
 #ifndef HASH4D_H
 #define HASH4D_H

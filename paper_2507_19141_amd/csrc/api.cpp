@@ -252,6 +252,7 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
     const size_t need = scatter_mask_bytes((int)n, g->L);
     if (!workspace || ws_bytes < need)
         return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    if (((uintptr_t)workspace) & 15u) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
     const DevGrid d = to_device(*g);
     int64_t rows[H4D_MAX_LEVELS];
     rows_of(*g, rows);
@@ -297,6 +298,7 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
     const size_t need = smooth_ws(g, table_dt, n);
     if (d_table && (!workspace || ws_bytes < need))
         return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    if (workspace && (((uintptr_t)workspace) & 15u)) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
     const DevGrid d = to_device(*g);
     const hipStream_t s = (hipStream_t)stream;
     // pass 1: loss and the feature difference d = G(x) - G(x + eps), level-major [L, n, F]
@@ -428,6 +430,7 @@ h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* param
     const size_t need = mlp_workspace_bytes(dt, m->in, m->out, (int)n);
     if (!workspace || ws_bytes < need)
         return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    if (((uintptr_t)workspace) & 15u) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
     return hip_status(launch_mlp_backward(dt, m->in, m->out, params, feat, Fk, ls, qs, (int)n, d_out, loss_scale,
                                           grad_scale, grad_scale, d_feat, ls, qs, d_params, workspace,
                                           (hipStream_t)stream),
@@ -490,6 +493,7 @@ h4d_status hash4d_deform_backward(const h4d_grid* g, const h4d_mlp* m, h4d_dtype
     const size_t need = deform_ws(g, m, dt, n);
     if (!workspace || ws_bytes < need)
         return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    if (((uintptr_t)workspace) & 15u) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
     const DevGrid d = to_device(*g);
     const hipStream_t s = (hipStream_t)stream;
     const int64_t ls = n * g->F, qs = g->F;

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_bmask(const BSeg* __restrict__ 
     if (q >= sg.n || l >= g.L) return;
     float4 x = sg.xyz[q];
     x.w = sg.t;
-    sg.mask[(int64_t)l * sg.n + q] = corner_tile_mask(g, tms[sg.scene], l, x);
+    sg.mask[(int64_t)l * mask_stride(sg.n) + q] = corner_tile_mask(g, tms[sg.scene], l, x);
 }
 
 constexpr int kBatchScatterBlock = 1024;  // one workgroup per CU (128 KiB tile), 16 wavefronts
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBatchScatterBlock) void k_bscatter(const BSeg* __r
     __syncthreads();
     for (int sgi = tl.seg0; sgi < tl.seg0 + tl.nseg; ++sgi) {
         const BSeg sg = segs[sgi];
-        masked_queue_loop<kBatchScatterBlock>(sg.n, sg.mask + (int64_t)l * sg.n, tl.bit, queue, [&](int q) {
+        masked_queue_loop<kBatchScatterBlock>(sg.n, sg.mask + (int64_t)l * mask_stride(sg.n), tl.bit, queue, [&](int q) {
             const float* gp = sg.d_feat + ((int64_t)l * sg.n + q) * F;
             float gv[F];
 #pragma unroll
@@ -495,7 +495,7 @@ h4d_status hash4d_batched_plan_create(h4d_batched_plan** out, const h4d_scene_de
     hipError_t e = hipMalloc((void**)&p->d_feat, std::max<int64_t>(dfeat_elems, 1) * sizeof(float));
     if (e != hipSuccess) return bail(plan_hip(e, "plan d_feat"));
     int64_t mask_elems = 0;
-    for (int s = 0; s < n_scenes; ++s) mask_elems += (int64_t)scenes[s].n_times * scenes[s].grid.L * scenes[s].n;
+    for (int s = 0; s < n_scenes; ++s) mask_elems += (int64_t)scenes[s].n_times * scenes[s].grid.L * mask_stride(scenes[s].n);
     if ((e = hipMalloc((void**)&p->masks, std::max<int64_t>(mask_elems, 1) * sizeof(uint32_t))) != hipSuccess)
         return bail(plan_hip(e, "plan masks"));
     int64_t mo = 0;
@@ -514,7 +514,7 @@ h4d_status hash4d_batched_plan_create(h4d_batched_plan** out, const h4d_scene_de
             b.d_feat = p->d_feat + dfo + k * seg_elems;
             b.d_table = d.d_table;
             b.mask = p->masks + mo;
-            mo += (int64_t)d.grid.L * d.n;
+            mo += (int64_t)d.grid.L * mask_stride(d.n);
             segs.push_back(b);
         }
         dfo += d.n_times * seg_elems;
@@ -542,7 +542,7 @@ h4d_status hash4d_batched_plan_create(h4d_batched_plan** out, const h4d_scene_de
                 for (int t = 0; t < P; ++t) {
                     const int64_t r = d.grid.offset[l] + (int64_t)t * tm.rows_per_tile;
                     const uint32_t cnt = (uint32_t)std::min<int64_t>(tm.rows_per_tile, d.grid.offset[l + 1] - r);
-                    tiles.push_back(BTile{sc, l, seg0, d.n_times, (uint32_t)r, cnt, 1u << ((t * 32) / P)});
+                    tiles.push_back(BTile{sc, l, seg0, d.n_times, (uint32_t)r, cnt, 1u << (t >> tm.bit_shift[l])});
                 }
             }
             seg0 += d.n_times;

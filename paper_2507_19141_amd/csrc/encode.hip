@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kEncodeBlock) void k_tile_mask(DevGrid g, TileMap t
                                       __fadd_rn(x.w, e.w));
         m |= corner_tile_mask(g, tm, l, xp);
     }
-    mask[(int64_t)l * n + q] = m;
+    mask[(int64_t)l * mask_stride(n) + q] = m;
 }
 
 // 1024 threads share each tile: the 128 KiB of LDS allows one workgroup per CU, and
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
     const uint32_t bit = tile_bit(tm, l, first);
     for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) tile[i] = G(0);
     __syncthreads();
-    masked_queue_loop<kScatterBlock>(n, mask + (int64_t)l * n, bit, queue, [&](int q) {
+    masked_queue_loop<kScatterBlock>(n, mask + (int64_t)l * mask_stride(n), bit, queue, [&](int q) {
         tile_query<G, F, PAIR>(g, l, xyzt, eps, src, lstride, qstride, scale, q, base, cnt, tile);
     });
     __syncthreads();
@@ -191,18 +191,21 @@ hipError_t launch_encode(const DevGrid& g, h4d_dtype dt, const void* table, cons
 TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes) {
     TileMap tm;
     memset(&tm, 0, sizeof tm);
-    tm.rows_per_tile = kTileBytes / (F * gbytes);
+    tm.rows_per_tile = kTileBytes / (F * gbytes);  // a power of two: F and gbytes are
+    while ((1 << tm.tile_shift) < tm.rows_per_tile) ++tm.tile_shift;
     int t = 0;
     for (int l = 0; l < g.L; ++l) {
         tm.tile_start[l] = t;
         tm.level_rows[l] = (int32_t)level_rows[l];
-        t += (int)((level_rows[l] + tm.rows_per_tile - 1) / tm.rows_per_tile);
+        const int P = (int)((level_rows[l] + tm.rows_per_tile - 1) / tm.rows_per_tile);
+        while (((P - 1) >> tm.bit_shift[l]) >= 32) ++tm.bit_shift[l];
+        t += P;
     }
     tm.tile_start[g.L] = t;
     return tm;
 }
 
-size_t scatter_mask_bytes(int n, int L) { return (size_t)n * L * sizeof(uint32_t); }
+size_t scatter_mask_bytes(int n, int L) { return (size_t)mask_stride(n) * L * sizeof(uint32_t); }
 
 template <typename G, int F, bool PAIR>
 static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt, const float* eps, int n,

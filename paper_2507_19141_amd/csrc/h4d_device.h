@@ -181,35 +181,83 @@ __device__ __forceinline__ void lds_add(float* p, float v) {
 }
 __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
 
+// Add (v0, v1) to two adjacent FP32 words of LDS (8-byte aligned) with one 64-bit
+// compare-and-swap loop.
+__device__ __forceinline__ void lds_add2(float* p, float v0, float v1) {
+    unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
+    unsigned long long seen = *reinterpret_cast<volatile unsigned long long*>(u);
+    while (true) {
+        const float a = __uint_as_float((unsigned int)seen) + v0;
+        const float b = __uint_as_float((unsigned int)(seen >> 32)) + v1;
+        const unsigned long long want =
+            (unsigned long long)__float_as_uint(a) | ((unsigned long long)__float_as_uint(b) << 32);
+        const unsigned long long prev = atomicCAS(u, seen, want);
+        if (prev == seen) break;
+        seen = prev;
+    }
+}
+
+// Add F values to one tile row.
+template <typename G, int F>
+__device__ __forceinline__ void lds_add_row(G* p, const G (&v)[F], G w) {
+    if constexpr (sizeof(G) == 4 && F % 2 == 0) {
+#pragma unroll
+        for (int f = 0; f < F; f += 2) lds_add2(p + f, w * v[f], w * v[f + 1]);
+    } else {
+#pragma unroll
+        for (int f = 0; f < F; ++f) lds_add(p + f, w * v[f]);
+    }
+}
+
 // Add w_c gv at the corners of x that fall in table rows [base, base + cnt) to an
-// LDS tile (row r at tile[(r - base) F]).
+// LDS tile (row r at tile[(r - base) F]).  Each lane walks only its own in-tile
+// corners (a bit mask), rebuilding row and weight of corner k from the per-axis
+// terms, so a wavefront issues LDS adds for as many corners as its busiest lane
+// has in the tile (typically one x-pair on a hashed level) instead of all 16.
 template <typename G, int F>
 __device__ __forceinline__ void tile_contrib(const DevGrid& g, int l, float4 x, const G (&gv)[F], uint32_t base,
                                              uint32_t cnt, G* tile) {
     const Cell c = level_cell(g, l, x);
     uint32_t row[16];
     level_rows(g, l, c, row);
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) m |= (uint32_t)((row[k] - base) < cnt) << k;
+    if (m == 0u) return;
     const G wx[2] = {G(1) - G(c.fx), G(c.fx)};
     const G wy[2] = {G(1) - G(c.fy), G(c.fy)};
     const G wz[2] = {G(1) - G(c.fz), G(c.fz)};
     const G wt[2] = {G(1) - G(c.ft), G(c.ft)};
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const uint32_t r = row[k] - base;
-        if (r < cnt) {
-            const G w = ((wx[k & 1] * wy[(k >> 1) & 1]) * wz[(k >> 2) & 1]) * wt[k >> 3];
-#pragma unroll
-            for (int f = 0; f < F; ++f) lds_add(tile + r * F + f, w * gv[f]);
+    // Per-axis terms of the lower corner; corner k adds the axis step where its bit
+    // is set.  Dense rows are their sum, hashed rows their XOR (Eq. 8).
+    const bool dense = (g.dense_bits >> l) & 1u;
+    const uint32_t S = (uint32_t)g.res_s[l] + 1u;
+    const uint32_t px = dense ? 1u : g.prime[0], py = dense ? S : g.prime[1];
+    const uint32_t pz = dense ? S * S : g.prime[2], pt = dense ? S * S * S : g.prime[3];
+    const uint32_t ax = (uint32_t)c.ix * px, ay = (uint32_t)c.iy * py, az = (uint32_t)c.iz * pz,
+                   at = (uint32_t)c.it * pt;
+    const uint32_t off = g.off[l];
+    while (m) {
+        const int k = __builtin_ctz(m);
+        m &= m - 1u;
+        const uint32_t hx = ax + ((k & 1) ? px : 0u), hy = ay + ((k & 2) ? py : 0u);
+        const uint32_t hz = az + ((k & 4) ? pz : 0u), ht = at + ((k & 8) ? pt : 0u);
+        uint32_t r;
+        if (dense) {
+            r = off + hx + hy + hz + ht;
+        } else {
+            const uint32_t h = hx ^ hy ^ hz ^ ht;
+            r = off + (g.tmask ? (h & g.tmask) : (h % g.T));
         }
+        r -= base;
+        const G w = ((wx[k & 1] * wy[(k >> 1) & 1]) * wz[(k >> 2) & 1]) * wt[k >> 3];
+        lds_add_row<G, F>(tile + r * F, gv, w);
     }
 }
 
-// Bit of the tile holding level-relative row rel_row: tile t of a level with P
-// tiles sets bit t*32/P of a query's mask.
+// Bit of the tile holding level-relative row rel_row.
 __device__ __forceinline__ uint32_t tile_bit(const TileMap& tm, int l, uint32_t rel_row) {
-    const uint32_t t = rel_row / (uint32_t)tm.rows_per_tile;
-    const uint32_t P = (uint32_t)(tm.tile_start[l + 1] - tm.tile_start[l]);
-    return 1u << ((t * 32u) / P);
+    return 1u << ((rel_row >> tm.tile_shift) >> tm.bit_shift[l]);
 }
 
 __device__ __forceinline__ uint32_t corner_tile_mask(const DevGrid& g, const TileMap& tm, int l, float4 x) {
@@ -222,17 +270,18 @@ __device__ __forceinline__ uint32_t corner_tile_mask(const DevGrid& g, const Til
     return m;
 }
 
-// Run work(q) for every q < n whose tile mask lmask[q] has `bit` set.  Each
-// wavefront scans its own interleaved slice of the queries (64 masks per step,
-// the next step's masks already in flight), compacts the hits into a private LDS
-// queue of 128 entries and runs work() on full 64-lane batches; no workgroup-wide
-// barrier is involved, so the wavefronts of a workgroup overlap freely.
 // Orders one wavefront's LDS queue writes before its reads by other lanes.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
+// Run work(q) for every q < n whose tile mask lmask[q] has `bit` set.  lmask is
+// 16-byte aligned and readable up to mask_stride(n) entries.  Each wavefront scans
+// its own interleaved slice of the masks, four per lane per step with one 16-byte
+// load (the next step's already in flight), compacts the hits into a private LDS
+// queue of 128 entries and runs work() on full 64-lane batches; no workgroup-wide
+// barrier is involved, so the wavefronts of a workgroup overlap freely.
 template <int BLOCK, typename Work>
 __device__ __forceinline__ void masked_queue_loop(int n, const uint32_t* __restrict__ lmask, uint32_t bit,
                                                   int* wqueue, Work work) {
@@ -240,28 +289,36 @@ __device__ __forceinline__ void masked_queue_loop(int n, const uint32_t* __restr
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     int* queue = wqueue + wave * 128;
+    const uint4* __restrict__ m4 = reinterpret_cast<const uint4*>(lmask);
+    const int groups = (n + 3) >> 2;
+    const uint64_t below = (1ull << lane) - 1ull;
     int qn = 0;
-    int q = wave * 64 + lane;
-    uint32_t m = q < n ? lmask[q] : 0u;
-    for (int q0 = wave * 64; q0 < n; q0 += BLOCK) {
-        const int qn_next = q + BLOCK;
-        const uint32_t m_next = qn_next < n ? lmask[qn_next] : 0u;
-        const bool hit = (m & bit) != 0u;
-        const uint64_t bal = __ballot(hit);
-        if (hit) queue[qn + __popcll(bal & ((1ull << lane) - 1ull))] = q;
-        qn += (int)__popcll(bal);
-        wave_sync();
-        if (qn >= 64) {
-            work(queue[lane]);
-            const int rest = qn - 64;
-            const int moved = lane < rest ? queue[64 + lane] : 0;
+    int gi = wave * 64 + lane;
+    uint4 cur = gi < groups ? m4[gi] : make_uint4(0u, 0u, 0u, 0u);
+    for (int g0 = wave * 64; g0 < groups; g0 += BLOCK) {
+        const int gn = gi + BLOCK;
+        const uint4 nxt = gn < groups ? m4[gn] : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t mm[4] = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = 4 * gi + j;
+            const bool hit = (mm[j] & bit) != 0u && q < n;
+            const uint64_t bal = __ballot(hit);
+            if (hit) queue[qn + __popcll(bal & below)] = q;
+            qn += (int)__popcll(bal);
             wave_sync();
-            if (lane < rest) queue[lane] = moved;
-            wave_sync();
-            qn = rest;
+            if (qn >= 64) {
+                work(queue[lane]);
+                const int rest = qn - 64;
+                const int moved = lane < rest ? queue[64 + lane] : 0;
+                wave_sync();
+                if (lane < rest) queue[lane] = moved;
+                wave_sync();
+                qn = rest;
+            }
         }
-        q = qn_next;
-        m = m_next;
+        gi = gn;
+        cur = nxt;
     }
     if (lane < qn) work(queue[lane]);
 }

@@ -38,13 +38,20 @@ hipError_t launch_encode(const DevGrid& g, h4d_dtype table_dt, const void* table
 // consecutive table rows), accumulating in LDS.  level_rows[l] = rows of level l.
 // eps != NULL: each query also subtracts its gradient at the corners of x + eps.
 constexpr int kTileBytes = 128 * 1024;
+// rows_per_tile = 2^tile_shift.  Tile t of level l sets bit t >> bit_shift[l] of
+// a query's mask (bit_shift[l] = 0 while the level has at most 32 tiles).
 struct TileMap {
     int32_t rows_per_tile;
+    int32_t tile_shift;
     int32_t tile_start[H4D_MAX_LEVELS + 1];
     int32_t level_rows[H4D_MAX_LEVELS];
+    int32_t bit_shift[H4D_MAX_LEVELS];
 };
 TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes);
-// Workspace of the scatter: one 32-bit tile mask per (query, level).
+// Workspace of the scatter: one 32-bit tile mask per (query, level), level-major
+// with the query count padded to a multiple of four so that every level starts on
+// a 16-byte boundary (the scan reads four masks per load).
+constexpr int64_t mask_stride(int64_t n) { return (n + 3) & ~(int64_t)3; }
 size_t scatter_mask_bytes(int n, int L);
 hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d_dtype grad_dt, const float* xyzt,
                                 const float* eps, int n, const void* src, int64_t lstride, int64_t qstride,

@@ -123,7 +123,11 @@ def test_entry_points_validate_without_launching():
     assert lib.hash4d_encode_backward(gp, 1, fake, 5, 0, fake, 1.0, fake, fake, 1 << 20, None) == -1  # F32/F64 grads
     assert lib.hash4d_encode_backward(gp, 0, fake, 5, 0, fake, 1.0, fake, fake, 4, None) == -1        # small workspace
     assert "workspace" in _lib.last_error()
+    assert lib.hash4d_encode_backward(gp, 0, fake, 5, 0, fake, 1.0, fake, fake + 8, 1 << 20, None) == -1  # misaligned
+    assert "aligned" in _lib.last_error()
     assert _lib.hash4d_encode_backward_workspace_bytes(g, 1000) == 1000 * 4 * 4
+    # masks are level-major with the query count padded to a multiple of four
+    assert _lib.hash4d_encode_backward_workspace_bytes(g, 1001) == 1004 * 4 * 4
     assert lib.hash4d_corner_indices(gp, fake, 5, None, None, None) == -1
     assert lib.hash4d_encode(None, 0, fake, fake, 5, 0, fake, None) == -1
     m = _lib.mlp_shape(32)
