@@ -284,7 +284,7 @@ typedef struct {
     int64_t queries;         /* sum over scenes of n * n_times */
     int32_t segments;        /* (scene, timestamp) pairs */
     int32_t encode_qpt, encode_lpb, encode_grid;
-    int32_t scatter_tiles, scatter_rows_per_tile; /* owner-computes scatter: one workgroup per tile */
+    int32_t scatter_tiles, scatter_rows_per_tile; /* owner-computes scatter: one workgroup per tile; rows of the largest tile */
     int32_t graph;           /* 1 if a HIP graph was captured */
     int32_t n_tuned;
     h4d_tune_result tuned[H4D_MAX_TUNED];

@@ -540,8 +540,8 @@ h4d_status hash4d_batched_plan_create(h4d_batched_plan** out, const h4d_scene_de
             for (int l = 0; l < d.grid.L; ++l) {
                 const int P = tm.tile_start[l + 1] - tm.tile_start[l];
                 for (int t = 0; t < P; ++t) {
-                    const int64_t r = d.grid.offset[l] + (int64_t)t * tm.rows_per_tile;
-                    const uint32_t cnt = (uint32_t)std::min<int64_t>(tm.rows_per_tile, d.grid.offset[l + 1] - r);
+                    const int64_t r = d.grid.offset[l] + ((int64_t)t << tm.tile_shift[l]);
+                    const uint32_t cnt = (uint32_t)std::min<int64_t>((int64_t)1 << tm.tile_shift[l], d.grid.offset[l + 1] - r);
                     tiles.push_back(BTile{sc, l, seg0, d.n_times, (uint32_t)r, cnt, 1u << (t >> tm.bit_shift[l])});
                 }
             }

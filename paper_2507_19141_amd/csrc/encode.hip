@@ -1,10 +1,9 @@
 // 4D hash encoder forward and backward kernels (DASH Section 4.2, Eqs. 8-9).
 //
-// Forward: one thread per (query, level).  The grid is level-major (blockIdx.y = level):
-// the hardware dispatches workgroups in linear order, so at any moment the chip
-// works on one or two levels and each XCD's L2 holds mostly that level's slice of
-// the table (4 MiB FP32 / 2 MiB BF16 for a 2^19-row, F = 2 level) instead of the
-// whole table.
+// Forward: one thread per (query, level).  Work items (level, 256 queries) are
+// placed on XCDs level by level (xcd_item), so each XCD's L2 holds mostly one
+// level's slice of the table (4 MiB FP32 / 2 MiB BF16 for a 2^19-row, F = 2 level)
+// instead of every XCD streaming the whole table through its L2.
 #include <string.h>
 
 #include "h4d_device.h"
@@ -19,8 +18,10 @@ __global__ __launch_bounds__(kEncodeBlock) void k_encode(DevGrid g, const TT* __
                                                          typename AccOf<TT>::type* __restrict__ out,
                                                          int64_t lstride, int64_t qstride) {
     using A = typename AccOf<TT>::type;
-    const int l = blockIdx.y;
-    const int q = blockIdx.x * kEncodeBlock + threadIdx.x;
+    const int chunks = (n + kEncodeBlock - 1) / kEncodeBlock;
+    int l, chunk;
+    if (!xcd_item(g.L * chunks, chunks, l, chunk)) return;
+    const int q = chunk * kEncodeBlock + threadIdx.x;
     if (q >= n) return;
     const Cell c = level_cell(g, l, xyzt[q]);
     uint32_t row[16];
@@ -121,9 +122,9 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
     int l = 0;
     while (l + 1 < g.L && (int)blockIdx.x >= tm.tile_start[l + 1]) ++l;
     const uint32_t t_in_level = (uint32_t)((int)blockIdx.x - tm.tile_start[l]);
-    const uint32_t first = t_in_level * (uint32_t)tm.rows_per_tile;
+    const uint32_t first = t_in_level << tm.tile_shift[l];
     const uint32_t base = g.off[l] + first;
-    const uint32_t cnt = min((uint32_t)tm.rows_per_tile, (uint32_t)tm.level_rows[l] - first);
+    const uint32_t cnt = min(1u << tm.tile_shift[l], (uint32_t)tm.level_rows[l] - first);
     const uint32_t bit = tile_bit(tm, l, first);
     for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) tile[i] = G(0);
     __syncthreads();
@@ -163,7 +164,8 @@ template <typename TT>
 static hipError_t encode_t(const DevGrid& g, const void* table, const float* xyzt, int n, void* out,
                            int64_t ls, int64_t qs, hipStream_t s) {
     using A = typename AccOf<TT>::type;
-    const dim3 grid = level_major_grid(n, g.L), block(kEncodeBlock);
+    const int chunks = (n + kEncodeBlock - 1) / kEncodeBlock;
+    const dim3 grid((unsigned)(kXcds * xcd_items_per(g.L * chunks))), block(kEncodeBlock);
     const TT* t = static_cast<const TT*>(table);
     const float4* x = reinterpret_cast<const float4*>(xyzt);
     A* o = static_cast<A*>(out);
@@ -191,13 +193,16 @@ hipError_t launch_encode(const DevGrid& g, h4d_dtype dt, const void* table, cons
 TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes) {
     TileMap tm;
     memset(&tm, 0, sizeof tm);
-    tm.rows_per_tile = kTileBytes / (F * gbytes);  // a power of two: F and gbytes are
-    while ((1 << tm.tile_shift) < tm.rows_per_tile) ++tm.tile_shift;
+    tm.max_rows = kTileBytes / (F * gbytes);  // a power of two: F and gbytes are
     int t = 0;
     for (int l = 0; l < g.L; ++l) {
         tm.tile_start[l] = t;
         tm.level_rows[l] = (int32_t)level_rows[l];
-        const int P = (int)((level_rows[l] + tm.rows_per_tile - 1) / tm.rows_per_tile);
+        const int64_t want = (level_rows[l] + kTilesPerLevel - 1) / kTilesPerLevel;
+        int sh = 8;  // at least 256 rows per tile
+        while ((1 << sh) < tm.max_rows && ((int64_t)1 << sh) < want) ++sh;
+        tm.tile_shift[l] = sh;
+        const int P = (int)((level_rows[l] + (1 << sh) - 1) >> sh);
         while (((P - 1) >> tm.bit_shift[l]) >= 32) ++tm.bit_shift[l];
         t += P;
     }
@@ -212,7 +217,7 @@ static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt
                           const uint32_t* mask, const void* src, int64_t ls, int64_t qs, double scale, void* d_table,
                           hipStream_t s) {
     auto kern = k_scatter_tiled<G, F, PAIR>;
-    const size_t lds = (size_t)tm.rows_per_tile * F * sizeof(G);
+    const size_t lds = (size_t)tm.max_rows * F * sizeof(G);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(tm.tile_start[g.L]), dim3(kScatterBlock), lds, s, g, tm,

@@ -9,6 +9,24 @@
 
 namespace h4d {
 
+// XCD-aware placement of level-major work items (level, chunk of queries).  The
+// dispatcher hands workgroups to the eight XCDs round-robin by linear id, so
+// workgroup b runs on XCD b % 8.  XCD x takes the contiguous run [x per, (x+1) per)
+// of the level-major item list, so its L2 serves one level's slice of the table at
+// a time instead of every XCD fetching every level.  Launch kXcds * per workgroups.
+constexpr int kXcds = 8;
+__host__ __device__ constexpr int xcd_items_per(int items) { return (items + kXcds - 1) / kXcds; }
+__device__ __forceinline__ bool xcd_item(int items, int chunks, int& level, int& chunk) {
+    const int per = xcd_items_per(items);
+    const int b = (int)blockIdx.x;
+    const int s = b / kXcds, x = b % kXcds;
+    const int item = x * per + s;
+    if (s >= per || item >= items) return false;
+    level = item / chunks;
+    chunk = item - level * chunks;
+    return true;
+}
+
 // Clamp to [0, 1]; NaN fails both comparisons and becomes 0.
 __device__ __forceinline__ float clamp_unit(float x) {
     x = (x >= 0.0f) ? x : 0.0f;
@@ -257,7 +275,7 @@ __device__ __forceinline__ void tile_contrib(const DevGrid& g, int l, float4 x, 
 
 // Bit of the tile holding level-relative row rel_row.
 __device__ __forceinline__ uint32_t tile_bit(const TileMap& tm, int l, uint32_t rel_row) {
-    return 1u << ((rel_row >> tm.tile_shift) >> tm.bit_shift[l]);
+    return 1u << ((rel_row >> tm.tile_shift[l]) >> tm.bit_shift[l]);
 }
 
 __device__ __forceinline__ uint32_t corner_tile_mask(const DevGrid& g, const TileMap& tm, int l, float4 x) {

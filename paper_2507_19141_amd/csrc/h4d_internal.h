@@ -38,13 +38,17 @@ hipError_t launch_encode(const DevGrid& g, h4d_dtype table_dt, const void* table
 // consecutive table rows), accumulating in LDS.  level_rows[l] = rows of level l.
 // eps != NULL: each query also subtracts its gradient at the corners of x + eps.
 constexpr int kTileBytes = 128 * 1024;
-// rows_per_tile = 2^tile_shift.  Tile t of level l sets bit t >> bit_shift[l] of
-// a query's mask (bit_shift[l] = 0 while the level has at most 32 tiles).
+// Level l is cut into tiles of 2^tile_shift[l] rows, sized so that the level has
+// about kTilesPerLevel tiles (a tile's work is the level's updates over its tile
+// count, so every level's tiles weigh about the same), at most max_rows rows
+// (kTileBytes of gradient).  Tile t of level l sets bit t >> bit_shift[l] of a
+// query's mask (bit_shift[l] = 0 while the level has at most 32 tiles).
+constexpr int kTilesPerLevel = 32;
 struct TileMap {
-    int32_t rows_per_tile;
-    int32_t tile_shift;
+    int32_t max_rows;
     int32_t tile_start[H4D_MAX_LEVELS + 1];
     int32_t level_rows[H4D_MAX_LEVELS];
+    int32_t tile_shift[H4D_MAX_LEVELS];
     int32_t bit_shift[H4D_MAX_LEVELS];
 };
 TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes);
