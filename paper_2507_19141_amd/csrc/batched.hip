@@ -116,6 +116,12 @@ __global__ __launch_bounds__(kBatchBlock) void k_bmask(const BSeg* __restrict__ 
     sg.mask[(int64_t)l * mask_stride(sg.n) + q] = corner_tile_mask(g, tms[sg.scene], l, x);
 }
 
+template <int F>
+struct BQuery {
+    float4 x;
+    float gv[F];
+};
+
 constexpr int kBatchScatterBlock = 1024;  // one workgroup per CU (128 KiB tile), 16 wavefronts
 
 template <int F>
@@ -131,15 +137,24 @@ __global__ __launch_bounds__(kBatchScatterBlock) void k_bscatter(const BSeg* __r
     __syncthreads();
     for (int sgi = tl.seg0; sgi < tl.seg0 + tl.nseg; ++sgi) {
         const BSeg sg = segs[sgi];
-        masked_queue_loop<kBatchScatterBlock>(sg.n, sg.mask + (int64_t)l * mask_stride(sg.n), tl.bit, queue, [&](int q) {
-            const float* gp = sg.d_feat + ((int64_t)l * sg.n + q) * F;
-            float gv[F];
+        masked_queue_loop<kBatchScatterBlock>(
+            sg.n, sg.mask + (int64_t)l * mask_stride(sg.n), tl.bit, queue,
+            [&](int q) {
+                BQuery<F> b;
+                const float* gp = sg.d_feat + ((int64_t)l * sg.n + q) * F;
 #pragma unroll
-            for (int f = 0; f < F; ++f) gv[f] = gp[f] * scale;
-            float4 x = sg.xyz[q];
-            x.w = sg.t;
-            tile_contrib<float, F>(g, l, x, gv, tl.base, tl.cnt, tile);
-        });
+                for (int f = 0; f < F; ++f) b.gv[f] = gp[f];
+                b.x = sg.xyz[q];
+                return b;
+            },
+            [&](const BQuery<F>& b) {
+                float gv[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) gv[f] = b.gv[f] * scale;
+                float4 x = b.x;
+                x.w = sg.t;
+                tile_contrib<float, F>(g, l, x, gv, tl.base, tl.cnt, tile);
+            });
     }
     __syncthreads();
     float* out = segs[tl.seg0].d_table + (size_t)tl.base * F;

@@ -88,19 +88,36 @@ __global__ __launch_bounds__(kEncodeBlock) void k_tile_mask(DevGrid g, TileMap t
 constexpr int kScatterBlock = 1024;
 constexpr int kQueueCap = 2 * kScatterBlock;  // 128 entries per wavefront
 
+// What the scatter loads per queued query: position, gradient (and perturbation).
 template <typename G, int F, bool PAIR>
-__device__ __forceinline__ void tile_query(const DevGrid& g, int l, const float4* __restrict__ xyzt,
-                                           const float4* __restrict__ eps, const G* __restrict__ src,
-                                           int64_t lstride, int64_t qstride, G scale, int q, uint32_t base,
-                                           uint32_t cnt, G* tile) {
+struct TileQuery {
+    float4 x;
+    float4 e;  // used when PAIR
+    G gv[F];
+};
+
+template <typename G, int F, bool PAIR>
+__device__ __forceinline__ TileQuery<G, F, PAIR> tile_load(int l, const float4* __restrict__ xyzt,
+                                                           const float4* __restrict__ eps, const G* __restrict__ src,
+                                                           int64_t lstride, int64_t qstride, int q) {
+    TileQuery<G, F, PAIR> t;
     const G* gp = src + (int64_t)l * lstride + (int64_t)q * qstride;
+#pragma unroll
+    for (int f = 0; f < F; ++f) t.gv[f] = gp[f];
+    t.x = xyzt[q];
+    if constexpr (PAIR) t.e = eps[q];
+    return t;
+}
+
+template <typename G, int F, bool PAIR>
+__device__ __forceinline__ void tile_run(const DevGrid& g, int l, const TileQuery<G, F, PAIR>& t, G scale,
+                                         uint32_t base, uint32_t cnt, G* tile) {
     G gv[F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) gv[f] = gp[f] * scale;
-    const float4 x = xyzt[q];
-    tile_contrib<G, F>(g, l, x, gv, base, cnt, tile);
+    for (int f = 0; f < F; ++f) gv[f] = t.gv[f] * scale;
+    tile_contrib<G, F>(g, l, t.x, gv, base, cnt, tile);
     if constexpr (PAIR) {
-        const float4 e = eps[q];
+        const float4 x = t.x, e = t.e;
         const float4 xp = make_float4(__fadd_rn(x.x, e.x), __fadd_rn(x.y, e.y), __fadd_rn(x.z, e.z),
                                       __fadd_rn(x.w, e.w));
         G gm[F];
@@ -128,9 +145,10 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
     const uint32_t bit = tile_bit(tm, l, first);
     for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) tile[i] = G(0);
     __syncthreads();
-    masked_queue_loop<kScatterBlock>(n, mask + (int64_t)l * mask_stride(n), bit, queue, [&](int q) {
-        tile_query<G, F, PAIR>(g, l, xyzt, eps, src, lstride, qstride, scale, q, base, cnt, tile);
-    });
+    masked_queue_loop<kScatterBlock>(
+        n, mask + (int64_t)l * mask_stride(n), bit, queue,
+        [&](int q) { return tile_load<G, F, PAIR>(l, xyzt, eps, src, lstride, qstride, q); },
+        [&](const TileQuery<G, F, PAIR>& t) { tile_run<G, F, PAIR>(g, l, t, scale, base, cnt, tile); });
     __syncthreads();
     G* out = d_table + (size_t)base * F;
     for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) {

@@ -294,16 +294,19 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Run work(q) for every q < n whose tile mask lmask[q] has `bit` set.  lmask is
-// 16-byte aligned and readable up to mask_stride(n) entries.  Each wavefront scans
-// its own interleaved slice of the masks, four per lane per step with one 16-byte
-// load (the next step's already in flight), compacts the hits into a private LDS
-// queue of 128 entries and runs work() on full 64-lane batches; no workgroup-wide
+// Run run(load(q)) for every q < n whose tile mask lmask[q] has `bit` set.
+// lmask is 16-byte aligned and readable up to mask_stride(n) entries.  Each
+// wavefront scans its own interleaved slice of the masks, four per lane per step
+// with one 16-byte load (the next step's already in flight), and compacts the hits
+// into a private LDS queue of 128 entries.  Full 64-lane batches are software
+// pipelined: the loads of a batch (load) are issued before the previous batch is
+// processed (run), so their latency hides behind its LDS work.  No workgroup-wide
 // barrier is involved, so the wavefronts of a workgroup overlap freely.
-template <int BLOCK, typename Work>
+template <int BLOCK, typename Load, typename Run>
 __device__ __forceinline__ void masked_queue_loop(int n, const uint32_t* __restrict__ lmask, uint32_t bit,
-                                                  int* wqueue, Work work) {
+                                                  int* wqueue, Load load, Run run) {
     static_assert(BLOCK % 64 == 0, "whole wavefronts");
+    using S = decltype(load(0));
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     int* queue = wqueue + wave * 128;
@@ -311,6 +314,8 @@ __device__ __forceinline__ void masked_queue_loop(int n, const uint32_t* __restr
     const int groups = (n + 3) >> 2;
     const uint64_t below = (1ull << lane) - 1ull;
     int qn = 0;
+    bool have = false;  // a loaded batch waits in `pend` (wave-uniform)
+    S pend{};
     int gi = wave * 64 + lane;
     uint4 cur = gi < groups ? m4[gi] : make_uint4(0u, 0u, 0u, 0u);
     for (int g0 = wave * 64; g0 < groups; g0 += BLOCK) {
@@ -326,19 +331,26 @@ __device__ __forceinline__ void masked_queue_loop(int n, const uint32_t* __restr
             qn += (int)__popcll(bal);
             wave_sync();
             if (qn >= 64) {
-                work(queue[lane]);
+                const S fresh = load(queue[lane]);
                 const int rest = qn - 64;
                 const int moved = lane < rest ? queue[64 + lane] : 0;
                 wave_sync();
                 if (lane < rest) queue[lane] = moved;
                 wave_sync();
                 qn = rest;
+                if (have) run(pend);
+                pend = fresh;
+                have = true;
             }
         }
         gi = gn;
         cur = nxt;
     }
-    if (lane < qn) work(queue[lane]);
+    const bool tail = lane < qn;
+    S last{};
+    if (tail) last = load(queue[lane]);
+    if (have) run(pend);
+    if (tail) run(last);
 }
 
 }  // namespace h4d
