@@ -189,7 +189,9 @@ __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAd
 // still rounds once; the order of the adds is unspecified, as with any atomic.
 __device__ __forceinline__ void lds_add(float* p, float v) {
     unsigned int* u = reinterpret_cast<unsigned int*>(p);
-    unsigned int seen = *reinterpret_cast<volatile unsigned int*>(u);
+    // A plain load: a stale value only costs one more round of the loop (a volatile
+    // load would become a flat access that waits for every outstanding global load).
+    unsigned int seen = *u;
     while (true) {
         const unsigned int want = __float_as_uint(__uint_as_float(seen) + v);
         const unsigned int prev = atomicCAS(u, seen, want);
@@ -203,7 +205,7 @@ __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); 
 // compare-and-swap loop.
 __device__ __forceinline__ void lds_add2(float* p, float v0, float v1) {
     unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
-    unsigned long long seen = *reinterpret_cast<volatile unsigned long long*>(u);
+    unsigned long long seen = *u;
     while (true) {
         const float a = __uint_as_float((unsigned int)seen) + v0;
         const float b = __uint_as_float((unsigned int)(seen >> 32)) + v1;
