@@ -230,25 +230,28 @@ __device__ __forceinline__ void lds_add_row(G* p, const G (&v)[F], G w) {
 }
 
 // Add w_c gv at the corners of x that fall in table rows [base, base + cnt) to an
-// LDS tile (row r at tile[(r - base) F]).  Each lane walks only its own in-tile
-// corners (a bit mask), rebuilding row and weight of corner k from the per-axis
-// terms, so a wavefront issues LDS adds for as many corners as its busiest lane
-// has in the tile (typically one x-pair on a hashed level) instead of all 16.
+// LDS tile (row r at tile[(r - base) F]).  The corners are taken in x-pairs (2p,
+// 2p + 1: same y, z, t), which share a tile on hashed levels because pi_1 = 1
+// keeps them within a few rows.  Each lane walks only its own pairs with a corner
+// in the tile (a bit mask), rebuilding their rows and weights from the per-axis
+// terms, so a wavefront issues LDS adds for as many pairs as its busiest lane has
+// in the tile (typically one on a hashed level) instead of all sixteen corners.
 template <typename G, int F>
 __device__ __forceinline__ void tile_contrib(const DevGrid& g, int l, float4 x, const G (&gv)[F], uint32_t base,
                                              uint32_t cnt, G* tile) {
     const Cell c = level_cell(g, l, x);
     uint32_t row[16];
     level_rows(g, l, c, row);
-    uint32_t m = 0;
+    uint32_t pm = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) m |= (uint32_t)((row[k] - base) < cnt) << k;
-    if (m == 0u) return;
+    for (int p = 0; p < 8; ++p)
+        pm |= (uint32_t)(((row[2 * p] - base) < cnt) | ((row[2 * p + 1] - base) < cnt)) << p;
+    if (pm == 0u) return;
     const G wx[2] = {G(1) - G(c.fx), G(c.fx)};
     const G wy[2] = {G(1) - G(c.fy), G(c.fy)};
     const G wz[2] = {G(1) - G(c.fz), G(c.fz)};
     const G wt[2] = {G(1) - G(c.ft), G(c.ft)};
-    // Per-axis terms of the lower corner; corner k adds the axis step where its bit
+    // Per-axis terms of the lower corner; a corner adds the axis step where its bit
     // is set.  Dense rows are their sum, hashed rows their XOR (Eq. 8).
     const bool dense = (g.dense_bits >> l) & 1u;
     const uint32_t S = (uint32_t)g.res_s[l] + 1u;
@@ -257,21 +260,29 @@ __device__ __forceinline__ void tile_contrib(const DevGrid& g, int l, float4 x, 
     const uint32_t ax = (uint32_t)c.ix * px, ay = (uint32_t)c.iy * py, az = (uint32_t)c.iz * pz,
                    at = (uint32_t)c.it * pt;
     const uint32_t off = g.off[l];
-    while (m) {
-        const int k = __builtin_ctz(m);
-        m &= m - 1u;
-        const uint32_t hx = ax + ((k & 1) ? px : 0u), hy = ay + ((k & 2) ? py : 0u);
-        const uint32_t hz = az + ((k & 4) ? pz : 0u), ht = at + ((k & 8) ? pt : 0u);
-        uint32_t r;
+    while (pm) {
+        const int p = __builtin_ctz(pm);
+        pm &= pm - 1u;
+        const uint32_t hy = ay + ((p & 1) ? py : 0u), hz = az + ((p & 2) ? pz : 0u), ht = at + ((p & 4) ? pt : 0u);
+        uint32_t r0, r1;
         if (dense) {
-            r = off + hx + hy + hz + ht;
+            r0 = off + ax + hy + hz + ht;
+            r1 = r0 + 1u;
         } else {
-            const uint32_t h = hx ^ hy ^ hz ^ ht;
-            r = off + (g.tmask ? (h & g.tmask) : (h % g.T));
+            const uint32_t H = hy ^ hz ^ ht, h0 = ax ^ H, h1 = (ax + px) ^ H;
+            if (g.tmask) {
+                r0 = off + (h0 & g.tmask);
+                r1 = off + (h1 & g.tmask);
+            } else {
+                r0 = off + h0 % g.T;
+                r1 = off + h1 % g.T;
+            }
         }
-        r -= base;
-        const G w = ((wx[k & 1] * wy[(k >> 1) & 1]) * wz[(k >> 2) & 1]) * wt[k >> 3];
-        lds_add_row<G, F>(tile + r * F, gv, w);
+        r0 -= base;
+        r1 -= base;
+        const G vy = wy[p & 1], vz = wz[(p >> 1) & 1], vt = wt[p >> 2];
+        if (r0 < cnt) lds_add_row<G, F>(tile + r0 * F, gv, ((wx[0] * vy) * vz) * vt);
+        if (r1 < cnt) lds_add_row<G, F>(tile + r1 * F, gv, ((wx[1] * vy) * vz) * vt);
     }
 }
 
