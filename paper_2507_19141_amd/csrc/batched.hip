@@ -126,12 +126,14 @@ constexpr int kBatchScatterBlock = 1024;  // one workgroup per CU (128 KiB tile)
 
 template <int F>
 __global__ __launch_bounds__(kBatchScatterBlock) void k_bscatter(const BSeg* __restrict__ segs, const DevGrid* __restrict__ grids,
+                                                                 const TileMap* __restrict__ tms,
                                                                  const BTile* __restrict__ tiles, float scale) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int queue[2 * kBatchScatterBlock];
     float* tile = reinterpret_cast<float*>(smem);
     const BTile tl = tiles[blockIdx.x];
     const DevGrid& g = grids[tl.scene];
+    const TileMap& tm = tms[tl.scene];
     const int l = tl.level;
     for (uint32_t i = threadIdx.x; i < tl.cnt * F; i += kBatchScatterBlock) tile[i] = 0.f;
     __syncthreads();
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(kBatchScatterBlock) void k_bscatter(const BSeg* __r
                 for (int f = 0; f < F; ++f) gv[f] = b.gv[f] * scale;
                 float4 x = b.x;
                 x.w = sg.t;
-                tile_contrib<float, F>(g, l, x, gv, tl.base, tl.cnt, tile);
+                tile_contrib<float, F>(g, tm, l, x, gv, tl.base, tl.cnt, tile);
             });
     }
     __syncthreads();
@@ -286,7 +288,7 @@ static hipError_t launch_bscatter(const h4d_batched_plan& p, float scale, hipStr
         hipError_t e = hipFuncSetAttribute((const void*)k_bscatter<FF>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                            (int)lds);                                                            \
         if (e != hipSuccess) return e;                                                                           \
-        hipLaunchKernelGGL((k_bscatter<FF>), grid, block, lds, st, p.segs, p.grids, p.tiles, scale);             \
+        hipLaunchKernelGGL((k_bscatter<FF>), grid, block, lds, st, p.segs, p.grids, p.tms, p.tiles, scale);             \
     } while (0)
     switch (F) {
         case 1: H4D_BSCA(1); break;

@@ -110,12 +110,12 @@ __device__ __forceinline__ TileQuery<G, F, PAIR> tile_load(int l, const float4* 
 }
 
 template <typename G, int F, bool PAIR>
-__device__ __forceinline__ void tile_run(const DevGrid& g, int l, const TileQuery<G, F, PAIR>& t, G scale,
-                                         uint32_t base, uint32_t cnt, G* tile) {
+__device__ __forceinline__ void tile_run(const DevGrid& g, const TileMap& tm, int l, const TileQuery<G, F, PAIR>& t,
+                                         G scale, uint32_t base, uint32_t cnt, G* tile) {
     G gv[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) gv[f] = t.gv[f] * scale;
-    tile_contrib<G, F>(g, l, t.x, gv, base, cnt, tile);
+    tile_contrib<G, F>(g, tm, l, t.x, gv, base, cnt, tile);
     if constexpr (PAIR) {
         const float4 x = t.x, e = t.e;
         const float4 xp = make_float4(__fadd_rn(x.x, e.x), __fadd_rn(x.y, e.y), __fadd_rn(x.z, e.z),
@@ -123,7 +123,7 @@ __device__ __forceinline__ void tile_run(const DevGrid& g, int l, const TileQuer
         G gm[F];
 #pragma unroll
         for (int f = 0; f < F; ++f) gm[f] = -gv[f];
-        tile_contrib<G, F>(g, l, xp, gm, base, cnt, tile);
+        tile_contrib<G, F>(g, tm, l, xp, gm, base, cnt, tile);
     }
 }
 
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
     masked_queue_loop<kScatterBlock>(
         n, mask + (int64_t)l * mask_stride(n), bit, queue,
         [&](int q) { return tile_load<G, F, PAIR>(l, xyzt, eps, src, lstride, qstride, q); },
-        [&](const TileQuery<G, F, PAIR>& t) { tile_run<G, F, PAIR>(g, l, t, scale, base, cnt, tile); });
+        [&](const TileQuery<G, F, PAIR>& t) { tile_run<G, F, PAIR>(g, tm, l, t, scale, base, cnt, tile); });
     __syncthreads();
     G* out = d_table + (size_t)base * F;
     for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) {
@@ -220,6 +220,10 @@ TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gb
         int sh = 8;  // at least 256 rows per tile
         while ((1 << sh) < tm.max_rows && ((int64_t)1 << sh) < want) ++sh;
         tm.tile_shift[l] = sh;
+        const bool hashed = !((g.dense_bits >> l) & 1u);
+        if (hashed && g.tmask != 0u && g.prime[0] == 1u && level_rows[l] >= ((int64_t)1 << sh) &&
+            2 * (int64_t)g.res_s[l] <= ((int64_t)1 << sh))
+            tm.pair_cotiled |= 1u << l;
         const int P = (int)((level_rows[l] + (1 << sh) - 1) >> sh);
         while (((P - 1) >> tm.bit_shift[l]) >= 32) ++tm.bit_shift[l];
         t += P;

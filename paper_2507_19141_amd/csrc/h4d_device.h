@@ -237,15 +237,30 @@ __device__ __forceinline__ void lds_add_row(G* p, const G (&v)[F], G w) {
 // terms, so a wavefront issues LDS adds for as many pairs as its busiest lane has
 // in the tile (typically one on a hashed level) instead of all sixteen corners.
 template <typename G, int F>
-__device__ __forceinline__ void tile_contrib(const DevGrid& g, int l, float4 x, const G (&gv)[F], uint32_t base,
-                                             uint32_t cnt, G* tile) {
+__device__ __forceinline__ void tile_contrib(const DevGrid& g, const TileMap& tm, int l, float4 x,
+                                             const G (&gv)[F], uint32_t base, uint32_t cnt, G* tile) {
     const Cell c = level_cell(g, l, x);
-    uint32_t row[16];
-    level_rows(g, l, c, row);
+    const bool cotiled = (tm.pair_cotiled >> l) & 1u;
     uint32_t pm = 0;
+    if (cotiled) {
+        // both corners of a pair share the tile: test the lower-x corner only
+        const uint32_t hx = (uint32_t)c.ix;  // pi_1 = 1
+        const uint32_t hy0 = (uint32_t)c.iy * g.prime[1], hy1 = hy0 + g.prime[1];
+        const uint32_t hz0 = (uint32_t)c.iz * g.prime[2], hz1 = hz0 + g.prime[2];
+        const uint32_t ht0 = (uint32_t)c.it * g.prime[3], ht1 = ht0 + g.prime[3];
+        const uint32_t rel = base - g.off[l];
 #pragma unroll
-    for (int p = 0; p < 8; ++p)
-        pm |= (uint32_t)(((row[2 * p] - base) < cnt) | ((row[2 * p + 1] - base) < cnt)) << p;
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t h = hx ^ ((p & 1) ? hy1 : hy0) ^ ((p & 2) ? hz1 : hz0) ^ ((p & 4) ? ht1 : ht0);
+            pm |= (uint32_t)(((h & g.tmask) - rel) < cnt) << p;
+        }
+    } else {
+        uint32_t row[16];
+        level_rows(g, l, c, row);
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+            pm |= (uint32_t)(((row[2 * p] - base) < cnt) | ((row[2 * p + 1] - base) < cnt)) << p;
+    }
     if (pm == 0u) return;
     const G wx[2] = {G(1) - G(c.fx), G(c.fx)};
     const G wy[2] = {G(1) - G(c.fy), G(c.fy)};
@@ -281,8 +296,8 @@ __device__ __forceinline__ void tile_contrib(const DevGrid& g, int l, float4 x, 
         r0 -= base;
         r1 -= base;
         const G vy = wy[p & 1], vz = wz[(p >> 1) & 1], vt = wt[p >> 2];
-        if (r0 < cnt) lds_add_row<G, F>(tile + r0 * F, gv, ((wx[0] * vy) * vz) * vt);
-        if (r1 < cnt) lds_add_row<G, F>(tile + r1 * F, gv, ((wx[1] * vy) * vz) * vt);
+        if (cotiled || r0 < cnt) lds_add_row<G, F>(tile + r0 * F, gv, ((wx[0] * vy) * vz) * vt);
+        if (cotiled || r1 < cnt) lds_add_row<G, F>(tile + r1 * F, gv, ((wx[1] * vy) * vz) * vt);
     }
 }
 
@@ -293,9 +308,19 @@ __device__ __forceinline__ uint32_t tile_bit(const TileMap& tm, int l, uint32_t 
 
 __device__ __forceinline__ uint32_t corner_tile_mask(const DevGrid& g, const TileMap& tm, int l, float4 x) {
     const Cell c = level_cell(g, l, x);
+    uint32_t m = 0;
+    if ((tm.pair_cotiled >> l) & 1u) {  // the lower-x corner of each pair decides
+        const uint32_t hx = (uint32_t)c.ix;
+        const uint32_t hy0 = (uint32_t)c.iy * g.prime[1], hy1 = hy0 + g.prime[1];
+        const uint32_t hz0 = (uint32_t)c.iz * g.prime[2], hz1 = hz0 + g.prime[2];
+        const uint32_t ht0 = (uint32_t)c.it * g.prime[3], ht1 = ht0 + g.prime[3];
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+            m |= tile_bit(tm, l, (hx ^ ((p & 1) ? hy1 : hy0) ^ ((p & 2) ? hz1 : hz0) ^ ((p & 4) ? ht1 : ht0)) & g.tmask);
+        return m;
+    }
     uint32_t row[16];
     level_rows(g, l, c, row);
-    uint32_t m = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) m |= tile_bit(tm, l, row[k] - g.off[l]);
     return m;

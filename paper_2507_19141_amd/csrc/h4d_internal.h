@@ -50,6 +50,10 @@ struct TileMap {
     int32_t level_rows[H4D_MAX_LEVELS];
     int32_t tile_shift[H4D_MAX_LEVELS];
     int32_t bit_shift[H4D_MAX_LEVELS];
+    // Bit l set: on level l both corners of every x-pair lie in the same full tile
+    // (hashed, T a power of two of at least one tile, pi_1 = 1 and 2 N_s <= tile
+    // rows: the pair's hashes differ only in bits below log2(2 N_s)).
+    uint32_t pair_cotiled;
 };
 TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes);
 // Workspace of the scatter: one 32-bit tile mask per (query, level), level-major

@@ -195,6 +195,30 @@ def test_encode_backward_f64():
     scaled_close(got, O.encode_backward(x, gf, og), O.encode_backward(x, np.abs(gf), og), 1e-12, "d_table f64")
 
 
+# Tiling regimes of the owner-computes scatter: hashed levels whose x-pairs may
+# straddle tiles (2 N_s above the tile rows), dense levels cut into many tiles (pairs
+# across tile boundaries), a non-power-of-two T (modulo hashing) and a tiny T.
+@pytest.mark.parametrize("F,T,rs,rt,n", [
+    (2, 1 << 12, (64, 1024), (2, 9), 3001),      # hashed, pairs not confined to one tile
+    (2, 1 << 13, (7, 7), (7, 7), 2999),           # one dense level of 4096 rows in 16 tiles
+    (1, 5000, (4, 600), (3, 40), 1501),           # modulo hashing, F = 1
+    (4, 1 << 16, (16, 256), (4, 64), 2503),       # dense then hashed, F = 4, pairs share tiles
+], ids=["hashed-straddle", "dense-many-tiles", "mod-T", "mixed-F4"])
+def test_encode_backward_tiling_regimes(F, T, rs, rt, n):
+    L = 3 if rs[0] != rs[1] else 1
+    rs_l = O.doubling_resolutions(rs[0], rs[1], L)
+    rt_l = O.doubling_resolutions(rt[0], rt[1], L)
+    og = O.make_grid(L, F, rs_l, rt_l, T)
+    lg = _lib.h4d_grid_init(L, F, rs_l, rt_l, T)
+    assert_same_layout(og, lg)
+    rng, x = synth.small_inputs(11, n)
+    x = np.concatenate([x, edge_points(og)])
+    gf = synth.upstream(x.shape[0], L * F, rng)
+    got = run_backward(lg, _lib.F32, x, gf, og.E, 0.75)
+    ref = O.encode_backward(x, gf, og, 0.75)
+    scaled_close(got, ref, O.encode_backward(x, np.abs(gf), og, 0.75), RTOL_GRAD, "d_table")
+
+
 def test_encode_backward_accumulates():
     import torch
     og, lg, x, _, rng = encoder_case(synth.ENCODER_SMALL, 1000, 9, edges=False)
