@@ -353,14 +353,25 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(MlpBatch batch, int o
     const int tps = (n + 15) / 16;
     const int ntiles = tps * sp.segs;
     const int stride = (sp.block1 - sp.block0) * kWaves;
-    for (int tile = ((int)blockIdx.x - sp.block0) * kWaves + (int)(threadIdx.x >> 6); tile < ntiles; tile += stride) {
+    // the features of the wavefront's next tile are loaded while it computes this one
+    auto load_tile = [&](int tile, V (&fv)[Sh::NI]) {
+        const int seg = tile / tps;
+        const int q = (tile - seg * tps) * 16 + j;
+        const V* __restrict__ feat = static_cast<const V*>(sp.feat) + (int64_t)seg * sp.feat_seg;
+        load_features<Pol, IN>(feat, sp.fv, q, tile < ntiles && q < n, fv);
+    };
+    int tile = ((int)blockIdx.x - sp.block0) * kWaves + (int)(threadIdx.x >> 6);
+    V next[Sh::NI];
+    load_tile(tile, next);
+    for (; tile < ntiles; tile += stride) {
         const int seg = tile / tps;
         const int q = (tile - seg * tps) * 16 + j;
         const bool valid = q < n;
-        const V* __restrict__ feat = static_cast<const V*>(sp.feat) + (int64_t)seg * sp.feat_seg;
         V* __restrict__ delta = static_cast<V*>(sp.delta) + (int64_t)seg * sp.out_seg;
         V fv[Sh::NI];
-        load_features<Pol, IN>(feat, sp.fv, q, valid, fv);
+#pragma unroll
+        for (int i = 0; i < Sh::NI; ++i) fv[i] = next[i];
+        load_tile(tile + stride, next);
         V h1[16], h2[16];
         trunk_forward<Pol, IN>(fr, fv, b1, b2, h1, h2);
         typename Pol::Acc a3 = Pol::zero();
@@ -465,25 +476,41 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int 
     const int tps = (n + 15) / 16;
     const int ntiles = tps * sp.segs;
     const int stride = (sp.block1 - sp.block0) * kWaves;
-    for (int tile = ((int)blockIdx.x - sp.block0) * kWaves + (int)(threadIdx.x >> 6); tile < ntiles; tile += stride) {
+    // the inputs of the wavefront's next tile are loaded while it computes this one
+    auto load_tile = [&](int tile, V (&fv)[Sh::NI], V (&go)[Sh::NO]) {
         const int seg = tile / tps;
         const int q = (tile - seg * tps) * 16 + j;
-        const bool valid = q < n;
+        const bool ok = tile < ntiles && q < n;
         const V* __restrict__ feat = static_cast<const V*>(sp.feat) + (int64_t)seg * sp.feat_seg;
-        V* __restrict__ d_feat = static_cast<V*>(sp.d_feat) + (int64_t)seg * sp.feat_seg;
         const V* __restrict__ d_out = static_cast<const V*>(sp.d_out) + (int64_t)seg * sp.out_seg;
-        V fv[Sh::NI];
-        load_features<Pol, IN>(feat, sp.fv, q, valid, fv);
-        V h1[16], h2[16];
-        trunk_forward<Pol, IN>(fr, fv, b1, b2, h1, h2);
-        // upstream gradient of the fused heads, scaled on load
-        V g3[Sh::NO];
+        load_features<Pol, IN>(feat, sp.fv, q, ok, fv);
 #pragma unroll
         for (int idx = 0; idx < Sh::NO; ++idx) {
             const int o = kb * Sh::NO + idx;
-            g3[idx] = (valid && o < out) ? d_out[(int64_t)q * out + o] * in_scale : V(0);
+            go[idx] = (ok && o < out) ? d_out[(int64_t)q * out + o] : V(0);
+        }
+    };
+    int tile = ((int)blockIdx.x - sp.block0) * kWaves + (int)(threadIdx.x >> 6);
+    V next_f[Sh::NI], next_g[Sh::NO];
+    load_tile(tile, next_f, next_g);
+    for (; tile < ntiles; tile += stride) {
+        const int seg = tile / tps;
+        const int q = (tile - seg * tps) * 16 + j;
+        const bool valid = q < n;
+        V* __restrict__ d_feat = static_cast<V*>(sp.d_feat) + (int64_t)seg * sp.feat_seg;
+        V fv[Sh::NI];
+        // upstream gradient of the fused heads, scaled on load
+        V g3[Sh::NO];
+#pragma unroll
+        for (int i = 0; i < Sh::NI; ++i) fv[i] = next_f[i];
+#pragma unroll
+        for (int idx = 0; idx < Sh::NO; ++idx) {
+            g3[idx] = next_g[idx] * in_scale;
             sb3[idx] += g3[idx];
         }
+        load_tile(tile + stride, next_f, next_g);
+        V h1[16], h2[16];
+        trunk_forward<Pol, IN>(fr, fv, b1, b2, h1, h2);
         // dH2^T = W3^T G3^T, masked by ReLU'(z2)
         Acc a[4];
 #pragma unroll
