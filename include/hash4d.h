@@ -14,6 +14,8 @@
  *  - n == 0 is valid and enqueues nothing.  n must not exceed 2^31 - 1.
  *  - Gradient outputs ACCUMULATE (+=) unless stated otherwise, so the caller
  *    zeroes them first.
+ *  - Tables [E, F] are aligned to their row size, at most 16 bytes (H4D_EINVAL
+ *    otherwise).
  *  - Positions `xyzt` are FP32 [n, 4] (x, y, z, t), 16-byte aligned.  Values are
  *    clamped to [0, 1] (NaN counts as 0); normalising scene coordinates into the
  *    unit cube is the caller's job.

@@ -87,6 +87,7 @@ DevGrid to_device(const h4d_grid& g) {
         d.off[l] = (uint32_t)g.offset[l];
         if (g.dense[l]) d.dense_bits |= 1u << l;
     }
+    d.rows = (uint32_t)g.offset[g.L];
     return d;
 }
 
@@ -94,6 +95,16 @@ static h4d_status check_xyzt(const float* xyzt, int64_t n) {
     if (n < 0 || n > kMaxN) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-1", (long long)n);
     if (n > 0 && !xyzt) return fail(H4D_EINVAL, "xyzt is NULL");
     if (((uintptr_t)xyzt) & 15u) return fail(H4D_EINVAL, "xyzt is not 16-byte aligned");
+    return H4D_OK;
+}
+
+// Tables are read a row at a time (up to 16-byte vector loads): align them to their
+// row size, capped at 16 bytes.
+static h4d_status check_table_alignment(const void* table, h4d_dtype dt, int F) {
+    const size_t el = dt == H4D_F64 ? 8 : dt == H4D_BF16 ? 2 : 4;
+    size_t a = el * (size_t)F;
+    if (a > 16) a = 16;
+    if (((uintptr_t)table) % a) return fail(H4D_EINVAL, "table is not aligned to its row size (%zu bytes)", a);
     return H4D_OK;
 }
 
@@ -228,6 +239,7 @@ h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* tabl
     if ((st = feat_strides(layout, n, g->L, g->F, &ls, &qs))) return st;
     if (n == 0) return H4D_OK;
     if (!table || !feat) return fail(H4D_EINVAL, "table or feat is NULL");
+    if ((st = check_table_alignment(table, table_dt, g->F))) return st;
     const DevGrid d = to_device(*g);
     return hip_status(launch_encode(d, table_dt, table, xyzt, (int)n, feat, ls, qs, (hipStream_t)stream),
                       "hash4d_encode");
@@ -293,6 +305,7 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
     if ((st = check_grid(g)) || (st = check_dtype(table_dt)) || (st = check_xyzt(xyzt, n))) return st;
     if (n == 0) return H4D_OK;
     if (!table || !eps || !loss) return fail(H4D_EINVAL, "table, eps or loss is NULL");
+    if ((st = check_table_alignment(table, table_dt, g->F))) return st;
     if (((uintptr_t)eps) & 15u) return fail(H4D_EINVAL, "eps is not 16-byte aligned");
     if (n * (int64_t)g->L * g->F > kMaxN) return fail(H4D_EINVAL, "n L F exceeds 2^31-1 features");
     const size_t need = smooth_ws(g, table_dt, n);
@@ -472,6 +485,7 @@ h4d_status hash4d_deform_forward(const h4d_grid* g, const h4d_mlp* m, h4d_dtype 
     if ((st = check_deform(g, m, dt, xyzt, n))) return st;
     if (n == 0) return H4D_OK;
     if (!table || !params || !feat || !delta) return fail(H4D_EINVAL, "NULL data pointer");
+    if ((st = check_table_alignment(table, dt, g->F))) return st;
     const DevGrid d = to_device(*g);
     const hipStream_t s = (hipStream_t)stream;
     const int64_t ls = n * g->F, qs = g->F;

@@ -12,7 +12,12 @@ namespace h4d {
 
 constexpr int kEncodeBlock = 256;
 
-template <typename TT, int F>
+// PAIRS (F = 2 FP32 / BF16 tables aligned to two rows): the two corners of an x-pair
+// (same y, z, t) sit in rows r0 and r0 ^ 1 whenever their hashes differ only in bit
+// 0 (pi_1 = 1 and an even lower x index; r1 = r0 + 1 on dense levels with r0 even),
+// and one aligned load of the row pair then serves both corners.  The loads change;
+// the arithmetic (and its order) does not.
+template <typename TT, int F, bool PAIRS>
 __global__ __launch_bounds__(kEncodeBlock) void k_encode(DevGrid g, const TT* __restrict__ table,
                                                          const float4* __restrict__ xyzt, int n,
                                                          typename AccOf<TT>::type* __restrict__ out,
@@ -27,8 +32,32 @@ __global__ __launch_bounds__(kEncodeBlock) void k_encode(DevGrid g, const TT* __
     uint32_t row[16];
     level_rows(g, l, c, row);
     A v[16][F];
+    if constexpr (PAIRS) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) RowLoad<TT, F, A>::load(table, row[k], v[k]);
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t r0 = row[2 * p], r1 = row[2 * p + 1];
+            const uint32_t a = r0 & ~1u;
+            if (a + 1u < g.rows) {
+                A lo[2], hi[2];
+                RowPairLoad<TT, A>::load(table, a, lo, hi);
+                const bool odd = r0 & 1u;
+#pragma unroll
+                for (int f = 0; f < 2; ++f) v[2 * p][f] = odd ? hi[f] : lo[f];
+                if (r1 == (r0 ^ 1u)) {
+#pragma unroll
+                    for (int f = 0; f < 2; ++f) v[2 * p + 1][f] = odd ? lo[f] : hi[f];
+                } else {
+                    RowLoad<TT, F, A>::load(table, r1, v[2 * p + 1]);
+                }
+            } else {
+                RowLoad<TT, F, A>::load(table, r0, v[2 * p]);
+                RowLoad<TT, F, A>::load(table, r1, v[2 * p + 1]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) RowLoad<TT, F, A>::load(table, row[k], v[k]);
+    }
     A w[16];
     level_weights<A>(c, w);
     A acc[F];
@@ -187,11 +216,16 @@ static hipError_t encode_t(const DevGrid& g, const void* table, const float* xyz
     const TT* t = static_cast<const TT*>(table);
     const float4* x = reinterpret_cast<const float4*>(xyzt);
     A* o = static_cast<A*>(out);
+    constexpr bool kPairable = !std::is_same<TT, double>::value;
+    const bool pairs = kPairable && g.F == 2 && ((uintptr_t)table % (2 * 2 * sizeof(TT))) == 0;
     switch (g.F) {
-        case 1: hipLaunchKernelGGL((k_encode<TT, 1>), grid, block, 0, s, g, t, x, n, o, ls, qs); break;
-        case 2: hipLaunchKernelGGL((k_encode<TT, 2>), grid, block, 0, s, g, t, x, n, o, ls, qs); break;
-        case 4: hipLaunchKernelGGL((k_encode<TT, 4>), grid, block, 0, s, g, t, x, n, o, ls, qs); break;
-        case 8: hipLaunchKernelGGL((k_encode<TT, 8>), grid, block, 0, s, g, t, x, n, o, ls, qs); break;
+        case 1: hipLaunchKernelGGL((k_encode<TT, 1, false>), grid, block, 0, s, g, t, x, n, o, ls, qs); break;
+        case 2:
+            if (pairs) hipLaunchKernelGGL((k_encode<TT, 2, kPairable>), grid, block, 0, s, g, t, x, n, o, ls, qs);
+            else hipLaunchKernelGGL((k_encode<TT, 2, false>), grid, block, 0, s, g, t, x, n, o, ls, qs);
+            break;
+        case 4: hipLaunchKernelGGL((k_encode<TT, 4, false>), grid, block, 0, s, g, t, x, n, o, ls, qs); break;
+        case 8: hipLaunchKernelGGL((k_encode<TT, 8, false>), grid, block, 0, s, g, t, x, n, o, ls, qs); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -175,6 +175,28 @@ struct RowLoad<double, F, A> {
     }
 };
 
+// Two consecutive rows (r, r + 1), r even, in one aligned load (F = 2 FP32 rows:
+// 16 bytes; F = 2 BF16 rows: 8 bytes).  lo receives row r, hi row r + 1.
+template <typename TT, typename A>
+struct RowPairLoad;
+
+template <typename A>
+struct RowPairLoad<float, A> {
+    __device__ __forceinline__ static void load(const float* __restrict__ t, uint32_t r, A (&lo)[2], A (&hi)[2]) {
+        const float4 a = *reinterpret_cast<const float4*>(t + (size_t)r * 2);
+        lo[0] = (A)a.x; lo[1] = (A)a.y; hi[0] = (A)a.z; hi[1] = (A)a.w;
+    }
+};
+
+template <typename A>
+struct RowPairLoad<bf16_t, A> {
+    __device__ __forceinline__ static void load(const bf16_t* __restrict__ t, uint32_t r, A (&lo)[2], A (&hi)[2]) {
+        const uint2 a = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(t) + (size_t)r * 2);
+        lo[0] = (A)__uint_as_float(a.x << 16); lo[1] = (A)__uint_as_float(a.x & 0xffff0000u);
+        hi[0] = (A)__uint_as_float(a.y << 16); hi[1] = (A)__uint_as_float(a.y & 0xffff0000u);
+    }
+};
+
 // Compute type of each table type: FP32 for F32/BF16 tables, FP64 for FP64 tables.
 template <typename TT> struct AccOf { using type = float; };
 template <> struct AccOf<double> { using type = double; };

@@ -20,6 +20,7 @@ struct DevGrid {
     int32_t res_s[H4D_MAX_LEVELS];
     int32_t res_t[H4D_MAX_LEVELS];
     uint32_t off[H4D_MAX_LEVELS]; // first row of level l (E F < 2^31, so rows fit 32 bits)
+    uint32_t rows;                // E, rows of the whole table
 };
 
 // Host-side conversion of a validated h4d_grid.

@@ -116,6 +116,8 @@ def test_entry_points_validate_without_launching():
     assert lib.hash4d_encode(gp, 0, None, fake, 5, 0, fake, None) == -1                # NULL table
     assert lib.hash4d_encode(gp, 0, fake, fake + 4, 5, 0, fake, None) == -1            # misaligned xyzt
     assert "aligned" in _lib.last_error()
+    assert lib.hash4d_encode(gp, 0, fake + 4, fake, 5, 0, fake, None) == -1            # table not row-aligned
+    assert "row size" in _lib.last_error()
     assert lib.hash4d_encode(gp, 7, fake, fake, 5, 0, fake, None) == -1                # unknown dtype
     assert lib.hash4d_encode(gp, 0, fake, fake, 5, 2, fake, None) == -1                # unknown layout
     assert lib.hash4d_encode(gp, 0, fake, fake, -1, 0, fake, None) == -1               # negative n

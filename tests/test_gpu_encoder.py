@@ -158,6 +158,28 @@ def test_encode_widths_sizes_and_ragged(F, T, n, L):
     assert np.array_equal(rows, O.corners(x, og)[0].astype(np.int32))
 
 
+@pytest.mark.parametrize("dt", [_lib.F32, _lib.BF16], ids=["f32", "bf16"])
+def test_encode_table_not_pair_aligned(dt):
+    # a table that starts one row into its allocation is row-aligned but not aligned
+    # to row pairs: the encoder takes its one-row loads, with the same results
+    import torch
+    og, lg, x, table, _ = encoder_case(synth.ENCODER_SMALL, 2048, 12)
+    if dt == _lib.BF16:
+        bits = O.bf16_bits(table).reshape(table.shape)
+        whole = torch.from_numpy(np.concatenate([np.zeros((1, og.F), np.uint16), bits]).view(np.int16)).cuda()
+        ref_table = O.bf16_value(bits)
+    else:
+        whole = dev(np.concatenate([np.zeros((1, og.F), np.float32), table]))
+        ref_table = table
+    shifted = whole[1:]
+    assert shifted.data_ptr() % (4 * shifted.element_size()) != 0
+    got = run_encode(lg, dt, shifted, x)
+    aligned = run_encode(lg, dt, whole[1:].clone(), x)
+    assert np.array_equal(got.view(np.uint32), aligned.view(np.uint32))
+    scaled_close(got, O.encode(x, ref_table, og), O.encode(x, np.abs(ref_table), og),
+                 RTOL_F32 if dt == _lib.F32 else 1e-5, "f_h")
+
+
 def test_encode_paper_scene_full_size_sampled():
     w = synth.PAPER_SCENE
     og, lg, x, table, _ = encoder_case(w, w.n, 5, edges=False)
