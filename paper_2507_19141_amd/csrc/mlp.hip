@@ -235,14 +235,19 @@ struct Frags {
 template <class Pol, int IN>
 __device__ void fill_frags(typename Pol::FE* lds, int count, const typename Pol::S* __restrict__ params, int out,
                            const ParamOff& po, typename Pol::S* stage) {
-    // One coalesced burst of the parameters into LDS first (many loads in flight),
-    // then the fragment permutation reads LDS only.
+    // With a staging buffer: one coalesced burst of the parameters into LDS first (many
+    // loads in flight), then the fragment permutation reads LDS only.  Without one: the
+    // permutation reads the (L2-resident) parameters directly.
+    const typename Pol::S* src = params;
+    if (stage) {
 #pragma unroll 8
-    for (int i = threadIdx.x; i < po.P; i += blockDim.x) stage[i] = params[i];
-    __syncthreads();
+        for (int i = threadIdx.x; i < po.P; i += blockDim.x) stage[i] = params[i];
+        __syncthreads();
+        src = stage;
+    }
     for (int t = threadIdx.x; t < count; t += blockDim.x) {
         const int s = frag_source<Pol, IN>(t, out, po);
-        lds[t] = s >= 0 ? Pol::to_frag(stage[s]) : typename Pol::FE(0);
+        lds[t] = s >= 0 ? Pol::to_frag(src[s]) : typename Pol::FE(0);
     }
 }
 
@@ -340,11 +345,8 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(MlpBatch batch, int o
     const typename Pol::S* __restrict__ params = static_cast<const typename Pol::S*>(sp.params);
     const ParamOff po(IN, out);
     Frags<Pol, IN, kLds> fr{reinterpret_cast<const typename Pol::FE*>(smem), params, out, po};
-    if constexpr (kLds) {
-        const size_t fbytes = ((size_t)Sh::FWD_FRAGS * sizeof(typename Pol::FE) + 15) / 16 * 16;
-        fill_frags<Pol, IN>(reinterpret_cast<typename Pol::FE*>(smem), Sh::FWD_FRAGS, params, out, po,
-                            reinterpret_cast<typename Pol::S*>(smem + fbytes));
-    }
+    if constexpr (kLds)  // no staging buffer: the forward keeps its LDS small for occupancy
+        fill_frags<Pol, IN>(reinterpret_cast<typename Pol::FE*>(smem), Sh::FWD_FRAGS, params, out, po, nullptr);
     __syncthreads();
     V b1[16], b2[16], b3[4];
     load_biases<Pol>(params, po, out, b1, b2, b3);
@@ -364,6 +366,9 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(MlpBatch batch, int o
     V next[Sh::NI];
     load_tile(tile, next);
     for (; tile < ntiles; tile += stride) {
+        // Weight fragments are read from LDS at each use rather than held in registers
+        // across the loop: the smaller register footprint fits three wavefronts per SIMD.
+        asm volatile("" ::: "memory");
         const int seg = tile / tps;
         const int q = (tile - seg * tps) * 16 + j;
         const bool valid = q < n;
@@ -738,9 +743,7 @@ static int mlp_blocks(int n, int cap) {
 template <class Pol, int IN>
 static size_t lds_forward(int out) {
     if (std::is_same<Pol, PolF64>::value) return 0;
-    const ParamOff po(IN, out);
-    return ((size_t)Shape<Pol, IN>::FWD_FRAGS * sizeof(typename Pol::FE) + 15) / 16 * 16 +
-           (size_t)po.P * sizeof(typename Pol::S);
+    return ((size_t)Shape<Pol, IN>::FWD_FRAGS * sizeof(typename Pol::FE) + 15) / 16 * 16;
 }
 
 template <class Pol, int IN>
