@@ -46,6 +46,11 @@ Readings of points the paper leaves open (each also listed in the design doc):
      (weights row-major, [out, in]).
  R7  Smoothness: L_r = lam / n * sum_i ||G(x_i) - G(clamp(x_i + eps_i))||^2,
      x + eps rounded in FP32, gradient through both terms.
+ R8  Input gradient (the step after the path: learned canonical positions through
+     the encoder): the derivative of Eq. 9 with respect to x_d in the cell the
+     forward selects (lower corner min(floor(x N), N - 1)), d w_c / d x_d =
+     (+N_d or -N_d) * prod of the other three factors; zero where the clamp is
+     active (x_d < 0, x_d > 1, NaN), the inner one-sided derivative at 0 and 1.
 
 Parity pins live in tests/test_oracle_*.py; "parity unpinned" marks what no pin
 covers (the prime set itself: any fixed set of large primes is a correct reading).
@@ -221,6 +226,49 @@ def encode_backward(xyzt: np.ndarray, d_feat: np.ndarray, grid: Grid, scale: flo
         for c in range(16):
             np.add.at(out, rows[:, l, c], scale * wts[:, l, c:c + 1] * gl)
     return out
+
+
+def corner_weight_derivatives(xyzt: np.ndarray, grid: Grid) -> np.ndarray:
+    """d w_c / d x_d of every corner at every level, [n, L, 16, 4] FP64 (R8).
+
+    w_c = prod_d (frac_d if corner c is upper along d else 1 - frac_d) with
+    frac_d = x_d N_d - i_d; its derivative along d is +N_d (upper) or -N_d (lower)
+    times the product of the other three factors, and 0 where the clamp is active.
+    """
+    x = np.asarray(xyzt, dtype=np.float32)
+    inside = (x >= np.float32(0.0)) & (x <= np.float32(1.0))   # NaN compares false
+    x32 = clamp_unit_f32(x)
+    n = x32.shape[0]
+    out = np.zeros((n, grid.L, 16, 4), dtype=np.float64)
+    for l in range(grid.L):
+        res = (grid.res_s[l],) * 3 + (grid.res_t[l],)
+        fr = [cell_position(x32[:, d], res[d])[1] for d in range(4)]
+        for c in range(16):
+            up = [(c >> d) & 1 for d in range(4)]
+            for d in range(4):
+                dw = np.full(n, float(res[d]) if up[d] else -float(res[d]))
+                for e in range(4):
+                    if e != d:
+                        dw = dw * (fr[e] if up[e] else 1.0 - fr[e])
+                out[:, l, c, d] = np.where(inside[:, d], dw, 0.0)
+    return out
+
+
+def encode_backward_input(xyzt: np.ndarray, table: np.ndarray, grid: Grid, d_feat: np.ndarray,
+                          scale: float = 1.0) -> np.ndarray:
+    """Gradient of <f_h, d_feat> with respect to the positions (R8), [n, 4] FP64:
+    d_x[q, d] = scale * sum_l sum_c (d w_c / d x_d) * sum_f theta[row_c, f] d_feat[q, l F + f]."""
+    rows, _ = corners(xyzt, grid)
+    dw = corner_weight_derivatives(xyzt, grid)
+    th = np.asarray(table, dtype=np.float64)
+    g = np.asarray(d_feat, dtype=np.float64)
+    out = np.zeros((rows.shape[0], 4), dtype=np.float64)
+    for l in range(grid.L):
+        gl = g[:, l * grid.F:(l + 1) * grid.F]
+        for c in range(16):
+            tg = np.sum(th[rows[:, l, c]] * gl, axis=1)
+            out += dw[:, l, c, :] * tg[:, None]
+    return scale * out
 
 
 # ----------------------------------------------------------------------------

@@ -320,3 +320,76 @@ def test_backward_matches_central_differences():
             e[r, f] = 1e-3
             fd = (np.sum(O.encode(x, th + e, g) * gf) - np.sum(O.encode(x, th - e, g) * gf)) / 2e-3
             assert abs(fd - grad[r, f]) <= 1e-9 * (1 + abs(fd))
+
+
+# ------------------------------------------------ input gradient (R8) ----
+def test_input_grad_affine_closed_form():
+    # theta(v) = a.v + b on a dense level gives f = a.(x N) + b, so d f / d x_d = a_d N_d
+    # everywhere inside the unit cube, including the boundaries 0 and 1.
+    Ns, Nt = 5, 3
+    g = O.make_grid(1, 2, [Ns], [Nt], 10 ** 6)
+    S = Ns + 1
+    v = np.array(np.meshgrid(np.arange(S), np.arange(S), np.arange(S), np.arange(Nt + 1), indexing="ij")).reshape(4, -1)
+    a = np.array([[0.3, -1.1], [2.0, 0.5], [-0.7, 0.25], [1.5, -3.0]])
+    table = np.zeros((g.E, 2))
+    table[O.dense_index(*v, Ns)] = v.T @ a + np.array([0.125, -2.0])
+    _, x = synth.small_inputs(18, 300)
+    x = np.concatenate([x, np.array([[0, 0, 0, 0], [1, 1, 1, 1], [1, 0, 0.5, 1]], np.float32)])
+    gf = np.array([0.75, -1.25])
+    N = np.array([Ns, Ns, Ns, Nt], dtype=np.float64)
+    got = O.encode_backward_input(x, table, g, np.tile(gf, (x.shape[0], 1)))
+    want = np.tile(N * (a @ gf), (x.shape[0], 1))
+    assert np.allclose(got, want, atol=1e-12, rtol=0)
+
+
+def fp64_level_value(x, table, g, rows):
+    """<theta, w> per level in FP64 with pos = x N in FP64, for the rows the oracle picked."""
+    n = x.shape[0]
+    out = np.zeros((n, g.L * g.F))
+    for l in range(g.L):
+        res = (g.res_s[l],) * 3 + (g.res_t[l],)
+        pos = [x[:, d].astype(np.float64) * res[d] for d in range(4)]
+        lo = [np.minimum(np.floor(p), r - 1) for p, r in zip(pos, res)]
+        for c in range(16):
+            w = np.ones(n)
+            for d in range(4):
+                fr = pos[d] - lo[d]
+                w *= fr if (c >> d) & 1 else 1.0 - fr
+            out[:, l * g.F:(l + 1) * g.F] += w[:, None] * table[rows[:, l, c]]
+    return out
+
+
+def test_input_grad_matches_central_differences():
+    # Inside a hypervoxel the encoder is multilinear in x, so central differences of an
+    # FP64 evaluation are exact up to rounding.  Points sit at least 1/8 of a cell away
+    # from every cell boundary at every level, so x +- h stays in the same cell.
+    g = O.make_grid(2, 2, [4, 8], [4, 8], 64)
+    assert g.dense == [False, False]
+    rng = np.random.default_rng(19)
+    x = ((rng.integers(0, 8, (40, 4)) + 0.5 + rng.uniform(-0.25, 0.25, (40, 4))) / 8).astype(np.float32)
+    th = rng.standard_normal((g.E, 2))
+    gf = rng.standard_normal((40, 4))
+    rows, _ = O.corners(x, g)
+    grad = O.encode_backward_input(x, th, g, gf)
+    h = 1e-6
+    for d in range(4):
+        e = np.zeros((1, 4))
+        e[0, d] = h
+        fp = np.sum(fp64_level_value(x + e, th, g, rows) * gf, axis=1)
+        fm = np.sum(fp64_level_value(x - e, th, g, rows) * gf, axis=1)
+        fd = (fp - fm) / (2 * h)
+        assert np.allclose(grad[:, d], fd, rtol=1e-6, atol=1e-6)
+
+
+def test_input_grad_is_zero_where_the_clamp_is_active():
+    g = small_grid()
+    rng = np.random.default_rng(20)
+    th = rng.standard_normal((g.E, 2))
+    x = np.array([[-0.5, 0.3, 0.6, 0.2], [0.4, 1.5, 0.1, 0.9], [0.2, 0.7, np.nan, 0.5],
+                  [0.3, 0.3, 0.3, np.inf]], np.float32)
+    gf = rng.standard_normal((4, 8))
+    grad = O.encode_backward_input(x, th, g, gf)
+    assert grad[0, 0] == 0 and grad[1, 1] == 0 and grad[2, 2] == 0 and grad[3, 3] == 0
+    assert np.count_nonzero(grad) == 12
+    # linear in d_feat and in the scale
+    assert np.allclose(O.encode_backward_input(x, th, g, 2 * gf, 0.5), grad, rtol=1e-15, atol=0)

@@ -136,3 +136,30 @@ def test_one_sided_smoothness_gradient_is_caught(monkeypatch):
     monkeypatch.setattr(O, "smoothness", one_sided)
     # the value check passes, the central differences do not
     expect_pin_failure(D.test_smoothness_value_and_central_differences)
+
+
+def test_input_grad_without_resolution_factor_is_caught(monkeypatch):
+    # d frac / d x = N was dropped: the derivative is taken in cell units
+    real = O.corner_weight_derivatives
+
+    def per_cell(xyzt, grid):
+        out = real(xyzt, grid)
+        for l in range(grid.L):
+            res = np.array((grid.res_s[l],) * 3 + (grid.res_t[l],), dtype=np.float64)
+            out[:, l] /= res
+        return out
+    monkeypatch.setattr(O, "corner_weight_derivatives", per_cell)
+    expect_pin_failure(E.test_input_grad_affine_closed_form)
+    expect_pin_failure(E.test_input_grad_matches_central_differences)
+
+
+def test_input_grad_ignoring_the_clamp_is_caught(monkeypatch):
+    # the derivative of the clamp taken as 1 everywhere (out-of-range inputs moved inside)
+    real = O.encode_backward_input
+
+    def unclamped(xyzt, table, grid, d_feat, scale=1.0):
+        x = np.asarray(xyzt, np.float32)
+        inside = np.where(np.isnan(x), np.float32(0.5), np.clip(x, np.float32(0.01), np.float32(0.99)))
+        return real(inside, table, grid, d_feat, scale)
+    monkeypatch.setattr(O, "encode_backward_input", unclamped)
+    expect_pin_failure(E.test_input_grad_is_zero_where_the_clamp_is_active)
