@@ -351,6 +351,28 @@ def batched_form(torch, _lib, synth, steps: int, warmup: int):
             "unbatched_ms_per_step": u_wall * 1e3 / u_steps}
 
 
+def input_grad_form(torch, _lib, path, steps: int):
+    """The next step beyond the path: the encoder's gradient with respect to the
+    positions (table FP32, level-major upstream gradients of the last step), timed
+    on its own with HIP events."""
+    n, w = path.n, path.w
+    d_xyzt = torch.zeros((n, 4), device="cuda")
+    call = lambda: _lib.hash4d_encode_backward_input(path.g, _lib.F32, path.table32, path.xyzt, n, path.d_feat, 1.0,
+                                                     d_xyzt, _lib.LEVEL_MAJOR)
+    for _ in range(3):
+        call()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        call()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    bytes_q = 16 + 16 * w.L * w.F * 4 + w.L * w.F * 4 + 16
+    return {"ms": ms, "value": n / (ms / 1e3), "unit": "queries/s", "algorithmic_bytes_per_query": bytes_q,
+            "achieved_GBps": bytes_q * n / (ms / 1e3) / 1e9, "kernel": "k_encode_input_grad"}
+
+
 def traffic_record(dominant: str):
     """HBM bytes per launch of the dominant part of the step, from the committed
     rocprofv3 --pmc summary (its fenced json block), if that was taken for the current
@@ -425,6 +447,7 @@ def main():
         "kernels_ms": per,
         "gpu_ms_per_step": gpu_ms,
     }
+    result["next"] = {"input_grad": input_grad_form(torch, _lib, fp32, args.steps)}
     del fp32
     torch.cuda.empty_cache()
     bf = Path(torch, _lib, synth, "bf16")

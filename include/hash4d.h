@@ -140,6 +140,19 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
                                   h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
                                   void* workspace, size_t ws_bytes, void* stream);
 
+/* Gradient of the encoder with respect to its input positions, for callers that
+ * learn the canonical positions through the encoder (the derivative of Eq. 9):
+ *   d_xyzt[q, d] += grad_scale * sum_l sum_f d_feat[q, l F + f] * d f_h[l F + f] / d x_d
+ * with d w_c / d x_d = +-N_d times the other three factors of w_c, in the cell the
+ * forward selects (lower corner min(floor(x N), N - 1)); zero along d where the
+ * clamp is active (x_d < 0, x_d > 1 or NaN), the inner one-sided derivative at 0
+ * and 1.  table_dt F32 / BF16: d_feat and d_xyzt FP32; F64: both FP64.
+ *   table [E, F]   d_feat n L F values in `layout`   d_xyzt [n, 4] (+=)
+ * One thread per query walks the levels; every (q, d) output has one writer. */
+h4d_status hash4d_encode_backward_input(const h4d_grid* g, h4d_dtype table_dt, const void* table,
+                                        const float* xyzt, int64_t n, h4d_layout layout, const void* d_feat,
+                                        float grad_scale, void* d_xyzt, void* stream);
+
 /* Test hook: the table row (level offset included) and FP32 weight of the 16
  * corners of every query and level.  Corner c is upper along x, y, z, t iff bit
  * 0, 1, 2, 3 of c is set.

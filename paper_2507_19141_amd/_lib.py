@@ -89,6 +89,7 @@ SIGNATURES = {
     "hash4d_encode": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _P]),
     "hash4d_encode_backward_workspace_bytes": (_SZ, [_GP, _I64]),
     "hash4d_encode_backward": (_I32, [_GP, _I32, _P, _I64, _I32, _P, _F32, _P, _P, _SZ, _P]),
+    "hash4d_encode_backward_input": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _F32, _P, _P]),
     "hash4d_corner_indices": (_I32, [_GP, _P, _I64, _P, _P, _P]),
     "hash4d_deform_apply": (_I32, [_P, _I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "smoothness_workspace_bytes": (_SZ, [_GP, _I32, _I64]),
@@ -200,6 +201,13 @@ def hash4d_encode_backward(g: Grid, grad_dt: int, xyzt, n: int, d_feat, grad_sca
     _check("hash4d_encode_backward",
            load().hash4d_encode_backward(ctypes.byref(g), grad_dt, ptr(xyzt), n, layout, ptr(d_feat), grad_scale,
                                          ptr(d_table), ptr(workspace), ws_bytes, stream_handle(stream)))
+
+
+def hash4d_encode_backward_input(g: Grid, table_dt: int, table, xyzt, n: int, d_feat, grad_scale: float, d_xyzt,
+                                 layout: int = QUERY_MAJOR, stream=None) -> None:
+    _check("hash4d_encode_backward_input",
+           load().hash4d_encode_backward_input(ctypes.byref(g), table_dt, ptr(table), ptr(xyzt), n, layout,
+                                               ptr(d_feat), grad_scale, ptr(d_xyzt), stream_handle(stream)))
 
 
 def hash4d_corner_indices(g: Grid, xyzt, n: int, rows, w, stream=None) -> None:

@@ -273,6 +273,25 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
                       "hash4d_encode_backward");
 }
 
+h4d_status hash4d_encode_backward_input(const h4d_grid* g, h4d_dtype table_dt, const void* table,
+                                        const float* xyzt, int64_t n, h4d_layout layout, const void* d_feat,
+                                        float grad_scale, void* d_xyzt, void* stream) {
+    g_last_error.clear();
+    h4d_status st;
+    int64_t ls, qs;
+    if ((st = check_grid(g)) || (st = check_dtype(table_dt)) || (st = check_xyzt(xyzt, n))) return st;
+    if ((st = feat_strides(layout, n, g->L, g->F, &ls, &qs))) return st;
+    if (n == 0) return H4D_OK;
+    if (!table || !d_feat || !d_xyzt) return fail(H4D_EINVAL, "table, d_feat or d_xyzt is NULL");
+    if ((st = check_table_alignment(table, table_dt, g->F))) return st;
+    if (((uintptr_t)d_xyzt) & (table_dt == H4D_F64 ? 31u : 15u))
+        return fail(H4D_EINVAL, "d_xyzt is not aligned to its row (%d bytes)", table_dt == H4D_F64 ? 32 : 16);
+    const DevGrid d = to_device(*g);
+    return hip_status(launch_encode_input_grad(d, table_dt, table, xyzt, (int)n, d_feat, ls, qs, (double)grad_scale,
+                                               d_xyzt, (hipStream_t)stream),
+                      "hash4d_encode_backward_input");
+}
+
 h4d_status hash4d_corner_indices(const h4d_grid* g, const float* xyzt, int64_t n, int32_t* rows, float* w,
                                  void* stream) {
     g_last_error.clear();

@@ -67,6 +67,10 @@ hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d
                                 double scale, void* d_table, void* mask_ws, hipStream_t s);
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w,
                                  hipStream_t s);
+// d_xyzt[q] += scale * d<f_h, d_feat>/dx (encode_input.hip).
+hipError_t launch_encode_input_grad(const DevGrid& g, h4d_dtype dt, const void* table, const float* xyzt, int n,
+                                    const void* d_feat, int64_t lstride, int64_t qstride, double scale, void* d_xyzt,
+                                    hipStream_t s);
 
 // ---- decoder launchers (mlp.hip) ----
 constexpr int kMaxMlpSpans = 16;

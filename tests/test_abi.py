@@ -131,6 +131,10 @@ def test_entry_points_validate_without_launching():
     # masks are level-major with the query count padded to a multiple of four
     assert _lib.hash4d_encode_backward_workspace_bytes(g, 1001) == 1004 * 4 * 4
     assert lib.hash4d_corner_indices(gp, fake, 5, None, None, None) == -1
+    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, 0, fake, 1.0, None, None) == -1   # NULL d_xyzt
+    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, 0, fake, 1.0, fake + 8, None) == -1
+    assert "d_xyzt" in _lib.last_error()
+    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 0, 0, None, 1.0, None, None) == 0     # n = 0
     assert lib.hash4d_encode(None, 0, fake, fake, 5, 0, fake, None) == -1
     m = _lib.mlp_shape(32)
     mp = _lib.ctypes.byref(m)
