@@ -28,10 +28,14 @@ __global__ __launch_bounds__(kInputGradBlock) void k_encode_input_grad(DevGrid g
     const bool in[4] = {x.x >= 0.f && x.x <= 1.f, x.y >= 0.f && x.y <= 1.f, x.z >= 0.f && x.z <= 1.f,
                         x.w >= 0.f && x.w <= 1.f};
     A acc[4] = {A(0), A(0), A(0), A(0)};
-    for (int l = 0; l < g.L; ++l) {
-        const Cell c = level_cell(g, l, x);
+    auto gather = [&](int l, A (&v)[16][F], Cell& c) {
+        c = level_cell(g, l, x);
         uint32_t row[16];
         level_rows(g, l, c, row);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) RowLoad<TT, F, A>::load(table, row[k], v[k]);
+    };
+    auto level = [&](int l, const A (&v)[16][F], const Cell& c) {
         const A* gp = d_feat + (int64_t)l * lstride + (int64_t)q * qstride;
         A gv[F];
 #pragma unroll
@@ -41,11 +45,9 @@ __global__ __launch_bounds__(kInputGradBlock) void k_encode_input_grad(DevGrid g
         A s[4] = {A(0), A(0), A(0), A(0)};
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            A v[F];
-            RowLoad<TT, F, A>::load(table, row[k], v);
             A tg = A(0);
 #pragma unroll
-            for (int f = 0; f < F; ++f) tg += v[f] * gv[f];
+            for (int f = 0; f < F; ++f) tg += v[k][f] * gv[f];
             const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1, bt = k >> 3;
             const A wx = w[0][bx], wy = w[1][by], wz = w[2][bz], wt = w[3][bt];
             const A pxy = wx * wy, pzt = wz * wt;
@@ -60,6 +62,23 @@ __global__ __launch_bounds__(kInputGradBlock) void k_encode_input_grad(DevGrid g
         acc[1] += Ns * s[1];
         acc[2] += Ns * s[2];
         acc[3] += Nt * s[3];
+    };
+    // Two levels per step: both levels' 32 row loads are in flight before either is
+    // reduced, which halves the chain of dependent gathers per thread.
+    int l = 0;
+    for (; l + 1 < g.L; l += 2) {
+        A va[16][F], vb[16][F];
+        Cell ca, cb;
+        gather(l, va, ca);
+        gather(l + 1, vb, cb);
+        level(l, va, ca);
+        level(l + 1, vb, cb);
+    }
+    if (l < g.L) {
+        A va[16][F];
+        Cell ca;
+        gather(l, va, ca);
+        level(l, va, ca);
     }
     A* o = d_xyzt + (int64_t)q * 4;
 #pragma unroll
