@@ -46,6 +46,11 @@ Readings of points the paper leaves open (each also listed in the design doc):
      (weights row-major, [out, in]).
  R7  Smoothness: L_r = lam / n * sum_i ||G(x_i) - G(clamp(x_i + eps_i))||^2,
      x + eps rounded in FP32, gradient through both terms.
+ R9  Optimiser step (not in the paper, which leaves the optimiser to its 3DGS base):
+     Adam with bias correction, step size lr / (1 - beta1^t), denominator
+     sqrt(v) / sqrt(1 - beta2^t) + eps, on the gradient times grad_scale (the
+     inverse loss scale).  "Lazy" form: rows whose whole gradient is zero are left
+     untouched (parameters and moments), the update of only the touched entries.
  R8  Input gradient (the step after the path: learned canonical positions through
      the encoder): the derivative of Eq. 9 with respect to x_d in the cell the
      forward selects (lower corner min(floor(x N), N - 1)), d w_c / d x_d =
@@ -402,3 +407,29 @@ def bf16_value(bits: np.ndarray) -> np.ndarray:
     """BF16 bit patterns to their exact FP64 values."""
     u = np.asarray(bits, dtype=np.uint16).astype(np.uint32) << np.uint32(16)
     return u.view(np.float32).astype(np.float64)
+
+
+# ----------------------------------------------------------------------------
+# Optimiser step (R9) -- the step after the table and decoder gradients
+# ----------------------------------------------------------------------------
+def adam_step(p, g, m, v, lr, beta1, beta2, eps, t, grad_scale=1.0, lazy_row=0):
+    """One Adam step in FP64; returns new (p, m, v).
+
+    g is multiplied by grad_scale first.  With lazy_row = R > 0 the arrays are rows
+    of R values and a row whose gradient is all zero keeps its parameters and moments.
+    """
+    p = np.asarray(p, np.float64).copy()
+    m = np.asarray(m, np.float64).copy()
+    v = np.asarray(v, np.float64).copy()
+    g = np.asarray(g, np.float64) * grad_scale
+    if lazy_row:
+        live = np.repeat(np.any(g.reshape(-1, lazy_row) != 0, axis=1), lazy_row)
+    else:
+        live = np.ones(p.shape, dtype=bool)
+    m_new = beta1 * m + (1.0 - beta1) * g
+    v_new = beta2 * v + (1.0 - beta2) * g * g
+    step_size = lr / (1.0 - beta1 ** t)
+    denom = np.sqrt(v_new) / math.sqrt(1.0 - beta2 ** t) + eps
+    p_new = p - step_size * m_new / denom
+    return (np.where(live, p_new, p), np.where(live, m_new, m), np.where(live, v_new, v))
+

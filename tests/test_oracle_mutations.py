@@ -163,3 +163,14 @@ def test_input_grad_ignoring_the_clamp_is_caught(monkeypatch):
         return real(inside, table, grid, d_feat, scale)
     monkeypatch.setattr(O, "encode_backward_input", unclamped)
     expect_pin_failure(E.test_input_grad_is_zero_where_the_clamp_is_active)
+
+
+def test_adam_without_bias_correction_is_caught(monkeypatch):
+    from tests import test_oracle_optim as Opt
+    real = O.adam_step
+
+    def uncorrected(p, g, m, v, lr, beta1, beta2, eps, t, grad_scale=1.0, lazy_row=0):
+        # t = 1e9 makes both bias corrections 1, i.e. drops them
+        return real(p, g, m, v, lr, beta1, beta2, eps, 10 ** 9, grad_scale, lazy_row)
+    monkeypatch.setattr(O, "adam_step", uncorrected)
+    expect_pin_failure(Opt.test_adam_matches_torch_adam_over_three_steps)
