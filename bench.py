@@ -373,6 +373,32 @@ def input_grad_form(torch, _lib, path, steps: int):
             "achieved_GBps": bytes_q * n / (ms / 1e3) / 1e9, "kernel": "k_encode_input_grad"}
 
 
+def adam_form(torch, _lib, E: int, F: int, steps: int):
+    """The optimiser step over the paper scene's FP32 table master (E x F values):
+    Adam on the touched rows, the BF16 copy and the gradient zeroing in one pass."""
+    count = E * F
+    p = torch.randn(count, device="cuda")
+    gr = torch.randn(count, device="cuda")
+    m = torch.zeros(count, device="cuda")
+    v = torch.zeros(count, device="cuda")
+    lo = torch.empty(count, dtype=torch.int16, device="cuda")
+    flags = _lib.ADAM_LAZY | _lib.ADAM_ZERO_GRAD
+    call = lambda t: _lib.h4d_adam_step(p, gr, m, v, count, 1e-3, 0.9, 0.999, 1e-15, t, 1 / 4096, lo, F, flags)
+    for t in range(1, 4):
+        call(t)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for t in range(steps):
+        call(4 + t)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    bytes_el = 4 * 4 + 3 * 4 + 2 + 4   # read p g m v; write p m v, the BF16 copy, the zeroed gradient
+    gbps = bytes_el * count / (ms / 1e3) / 1e9
+    return {"ms": ms, "elements": count, "algorithmic_bytes_per_element": bytes_el, "achieved_GBps": gbps,
+            "frac_of_hbm_peak": gbps / HBM_PEAK_GBPS, "kernel": "k_adam"}
+
+
 def traffic_record(dominant: str):
     """HBM bytes per launch of the dominant part of the step, from the committed
     rocprofv3 --pmc summary (its fenced json block), if that was taken for the current
@@ -447,7 +473,8 @@ def main():
         "kernels_ms": per,
         "gpu_ms_per_step": gpu_ms,
     }
-    result["next"] = {"input_grad": input_grad_form(torch, _lib, fp32, args.steps)}
+    result["next"] = {"input_grad": input_grad_form(torch, _lib, fp32, args.steps),
+                      "adam_table": adam_form(torch, _lib, fp32.E, fp32.w.F, args.steps)}
     del fp32
     torch.cuda.empty_cache()
     bf = Path(torch, _lib, synth, "bf16")

@@ -191,6 +191,31 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
  * BF16 form reads.  count elements; dst may not overlap src. */
 h4d_status h4d_cast_bf16(const float* src, uint16_t* dst, int64_t count, void* stream);
 
+/* ------------------------------------------------------ optimiser step ---- */
+
+/* Hyper-parameters of one Adam step (host struct). */
+typedef struct {
+    float lr, beta1, beta2, eps;
+    int32_t step;        /* t >= 1: the bias corrections use beta^t */
+    float grad_scale;    /* the gradient is multiplied by this first (1 / loss scale) */
+} h4d_adam;
+
+#define H4D_ADAM_LAZY 1       /* rows whose whole gradient is zero keep parameters and moments */
+#define H4D_ADAM_ZERO_GRAD 2  /* grad[] is set to 0 after use, ready for the next step */
+
+/* One Adam step over an FP32 master array (a table [E, F] or a decoder parameter
+ * vector), fused with the BF16 copy the next step's BF16 form reads and with the
+ * zeroing of the gradient: the step after the table and decoder gradients of
+ * training under Eq. 12 (the paper leaves the optimiser to its 3DGS base).
+ *   g = grad * grad_scale;  m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
+ *   p -= lr / (1 - b1^t) * m / (sqrt(v) / sqrt(1 - b2^t) + eps)
+ * params, grad, m, v: `count` FP32 values each, 16-byte aligned, not overlapping;
+ * bf16_out: NULL or `count` uint16 (8-byte aligned) receiving RNE BF16 of the new
+ * params.  row: the row length for H4D_ADAM_LAZY (1, 2, 4 or 8; count a multiple of
+ * it), ignored otherwise.  H4D_EINVAL on bad sizes, alignment or hyper-parameters. */
+h4d_status h4d_adam_step(float* params, float* grad, float* m, float* v, int64_t count, int32_t row,
+                         const h4d_adam* hp, uint16_t* bf16_out, int32_t flags, void* stream);
+
 /* *counter += number of NaN or Inf values in p[0, count) (the overflow check of
  * dynamic loss scaling).  The caller zeroes *counter (device int32). */
 h4d_status h4d_count_nonfinite(const float* p, int64_t count, int32_t* counter, void* stream);

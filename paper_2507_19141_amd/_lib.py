@@ -74,6 +74,13 @@ class BatchedInfo(ctypes.Structure):
                 ("n_tuned", ctypes.c_int32), ("tuned", TuneResult * MAX_TUNED)]
 
 
+class Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("step", ctypes.c_int32), ("grad_scale", ctypes.c_float)]
+
+
+ADAM_LAZY, ADAM_ZERO_GRAD = 1, 2
+
 _P = ctypes.c_void_p
 _I32, _I64, _F32, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
 _GP = ctypes.POINTER(Grid)
@@ -109,6 +116,7 @@ SIGNATURES = {
     "hash4d_batched_run": (_I32, [_P, _P]),
     "hash4d_batched_plan_info": (_I32, [_P, ctypes.POINTER(BatchedInfo)]),
     "hash4d_batched_plan_destroy": (None, [_P]),
+    "h4d_adam_step": (_I32, [_P, _P, _P, _P, _I64, _I32, ctypes.POINTER(Adam), _P, _I32, _P]),
     "h4d_probe_gather": (_I32, [_P, _I64, _I32, _I64, ctypes.c_uint32, _P, _P]),
     "h4d_probe_scatter": (_I32, [_P, _I64, _I64, ctypes.c_uint32, _I32, _P]),
     "h4d_probe_copy": (_I32, [_P, _P, _I64, _P]),
@@ -357,6 +365,13 @@ def h4d_probe_copy(src, dst, nbytes: int, stream=None) -> None:
 def h4d_probe_lds_atomic(blocks: int, per_thread: int, active: int, seed: int, mode: int, sink, stream=None) -> None:
     _check("h4d_probe_lds_atomic", load().h4d_probe_lds_atomic(blocks, per_thread, active, seed, mode, ptr(sink),
                                                                stream_handle(stream)))
+
+
+def h4d_adam_step(params, grad, m, v, count: int, lr: float, beta1: float, beta2: float, eps: float, step: int,
+                  grad_scale: float = 1.0, bf16_out=None, row: int = 1, flags: int = 0, stream=None) -> None:
+    hp = Adam(lr, beta1, beta2, eps, step, grad_scale)
+    _check("h4d_adam_step", load().h4d_adam_step(ptr(params), ptr(grad), ptr(m), ptr(v), count, row, ctypes.byref(hp),
+                                                 ptr(bf16_out), flags, stream_handle(stream)))
 
 
 def hip_runtimes_loaded() -> list:

@@ -350,6 +350,29 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
                       "smoothness_reg/scatter");
 }
 
+h4d_status h4d_adam_step(float* params, float* grad, float* m, float* v, int64_t count, int32_t row,
+                         const h4d_adam* hp, uint16_t* bf16_out, int32_t flags, void* stream) {
+    g_last_error.clear();
+    if (count < 0) return fail(H4D_EINVAL, "count=%lld is negative", (long long)count);
+    if (!hp) return fail(H4D_EINVAL, "hyper-parameters are NULL");
+    if (!(hp->lr >= 0.f) || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f) ||
+        !(hp->eps > 0.f) || hp->step < 1)
+        return fail(H4D_EINVAL, "need lr >= 0, 0 <= beta1, beta2 < 1, eps > 0, step >= 1");
+    if (flags & ~(H4D_ADAM_LAZY | H4D_ADAM_ZERO_GRAD)) return fail(H4D_EINVAL, "unknown flags 0x%x", flags);
+    const bool lazy = flags & H4D_ADAM_LAZY;
+    if (lazy && row != 1 && row != 2 && row != 4 && row != 8) return fail(H4D_EINVAL, "row must be 1, 2, 4 or 8");
+    if (lazy && count % row) return fail(H4D_EINVAL, "count is not a multiple of row");
+    if (count == 0) return H4D_OK;
+    if (!params || !grad || !m || !v) return fail(H4D_EINVAL, "params, grad, m or v is NULL");
+    if ((((uintptr_t)params) | ((uintptr_t)grad) | ((uintptr_t)m) | ((uintptr_t)v)) & 15u)
+        return fail(H4D_EINVAL, "params, grad, m and v must be 16-byte aligned");
+    if (bf16_out && (((uintptr_t)bf16_out) & 7u)) return fail(H4D_EINVAL, "bf16_out is not 8-byte aligned");
+    return hip_status(launch_adam(params, grad, m, v, count, lazy ? row : 1, hp->lr, hp->beta1, hp->beta2, hp->eps,
+                                  hp->step, hp->grad_scale, bf16_out, lazy, flags & H4D_ADAM_ZERO_GRAD,
+                                  (hipStream_t)stream),
+                      "h4d_adam_step");
+}
+
 h4d_status h4d_cast_bf16(const float* src, uint16_t* dst, int64_t count, void* stream) {
     g_last_error.clear();
     if (count < 0) return fail(H4D_EINVAL, "count=%lld < 0", (long long)count);

@@ -67,6 +67,10 @@ hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d
                                 double scale, void* d_table, void* mask_ws, hipStream_t s);
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w,
                                  hipStream_t s);
+// Fused Adam step + optional BF16 copy + gradient zeroing (optim.hip); row in {1,2,4,8}.
+hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, int row, double lr, double beta1,
+                       double beta2, double eps, int step, double grad_scale, uint16_t* lo, bool lazy, bool zero,
+                       hipStream_t s);
 // d_xyzt[q] += scale * d<f_h, d_feat>/dx (encode_input.hip).
 hipError_t launch_encode_input_grad(const DevGrid& g, h4d_dtype dt, const void* table, const float* xyzt, int n,
                                     const void* d_feat, int64_t lstride, int64_t qstride, double scale, void* d_xyzt,

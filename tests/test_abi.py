@@ -136,6 +136,18 @@ def test_entry_points_validate_without_launching():
     assert "d_xyzt" in _lib.last_error()
     assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 0, 0, None, 1.0, None, None) == 0     # n = 0
     assert lib.hash4d_encode(None, 0, fake, fake, 5, 0, fake, None) == -1
+    hp = _lib.Adam(1e-3, 0.9, 0.999, 1e-8, 1, 1.0)
+    hpp = _lib.ctypes.byref(hp)
+    assert lib.h4d_adam_step(fake, fake, fake, fake + 4, 8, 1, hpp, None, 0, None) == -1   # misaligned v
+    assert lib.h4d_adam_step(fake, fake, fake, fake, 9, 2, hpp, None, 1, None) == -1       # count % row
+    assert lib.h4d_adam_step(fake, fake, fake, fake, 8, 3, hpp, None, 1, None) == -1       # row 3
+    assert lib.h4d_adam_step(fake, fake, fake, fake, 8, 1, hpp, None, 4, None) == -1       # unknown flag
+    assert lib.h4d_adam_step(fake, fake, fake, fake, 8, 1, None, None, 0, None) == -1      # no hyper-parameters
+    bad = _lib.Adam(1e-3, 1.0, 0.999, 1e-8, 1, 1.0)
+    assert lib.h4d_adam_step(fake, fake, fake, fake, 8, 1, _lib.ctypes.byref(bad), None, 0, None) == -1  # beta1 = 1
+    bad = _lib.Adam(1e-3, 0.9, 0.999, 1e-8, 0, 1.0)
+    assert lib.h4d_adam_step(fake, fake, fake, fake, 8, 1, _lib.ctypes.byref(bad), None, 0, None) == -1  # step 0
+    assert lib.h4d_adam_step(None, None, None, None, 0, 1, hpp, None, 0, None) == 0        # count 0
     m = _lib.mlp_shape(32)
     mp = _lib.ctypes.byref(m)
     assert lib.deform_mlp_forward(mp, 0, fake, fake, 5, 1, 3, fake, None) == -1            # F must divide in
