@@ -51,6 +51,14 @@ Readings of points the paper leaves open (each also listed in the design doc):
      sqrt(v) / sqrt(1 - beta2^t) + eps, on the gradient times grad_scale (the
      inverse loss scale).  "Lazy" form: rows whose whole gradient is zero are left
      untouched (parameters and moments), the update of only the touched entries.
+ R10 Dynamic-static split (Section 4.1, the step before the path): the motion
+     magnitude ||dp|| is compared through its FP32 square s = (dx^2 + dy^2) + dz^2
+     (no fused multiply-add; the same order on the GPU), ordered by s's bit pattern
+     (NaN above +Inf).  n_d = floor(k / 100 * n) in FP64; tau is the (n_d + 1)-th
+     largest key (none when n_d >= n) and a Gaussian is dynamic iff its key is
+     strictly greater, so ties at tau are static.  The static constraint (Eq. 5) is
+     lam_s / N_s * sum over static ||dp|| (lam_s of Eq. 6 folded in), its gradient
+     lam_s / N_s * dp / ||dp|| (0 where dp = 0); N_s = 0 contributes nothing.
  R8  Input gradient (the step after the path: learned canonical positions through
      the encoder): the derivative of Eq. 9 with respect to x_d in the cell the
      forward selects (lower corner min(floor(x N), N - 1)), d w_c / d x_d =
@@ -432,4 +440,47 @@ def adam_step(p, g, m, v, lr, beta1, beta2, eps, t, grad_scale=1.0, lazy_row=0):
     denom = np.sqrt(v_new) / math.sqrt(1.0 - beta2 ** t) + eps
     p_new = p - step_size * m_new / denom
     return (np.where(live, p_new, p), np.where(live, m_new, m), np.where(live, v_new, v))
+
+
+# ----------------------------------------------------------------------------
+# Dynamic-static decomposition (R10) -- Section 4.1, Eqs. 3-5
+# ----------------------------------------------------------------------------
+def linear_motion(p, t, dp):
+    """Eq. 4: p(t) = p + t dp (FP64)."""
+    return np.asarray(p, np.float64) + np.asarray(t, np.float64)[:, None] * np.asarray(dp, np.float64)
+
+
+def motion_keys(dp) -> np.ndarray:
+    """The FP32 squared motion magnitude of each Gaussian as a uint32 sort key (R10)."""
+    d = np.asarray(dp, dtype=np.float32)
+    s = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]).astype(np.float32)
+    s = (s + d[:, 2] * d[:, 2]).astype(np.float32)
+    return s.view(np.uint32)
+
+
+def decompose(dp, k_percent: float, lam_s: float = 1.0):
+    """Self-supervised split and static constraint (R10).
+
+    Returns (dynamic indices ascending int64, loss FP64, d_dp [n, 3] FP64).
+    """
+    d = np.asarray(dp, dtype=np.float32)
+    n = d.shape[0]
+    key = motion_keys(d)
+    n_d = int(math.floor(k_percent / 100.0 * n))
+    if n_d >= n:
+        dynamic = np.ones(n, dtype=bool)
+    else:
+        tau = np.sort(key)[::-1][n_d]
+        dynamic = key > tau
+    static = ~dynamic
+    n_s = int(static.sum())
+    d64 = d.astype(np.float64)
+    mag = np.sqrt(np.sum(d64 * d64, axis=1))
+    grad = np.zeros((n, 3))
+    loss = 0.0
+    if n_s:
+        loss = lam_s / n_s * float(mag[static].sum())
+        live = static & (mag > 0)
+        grad[live] = lam_s / n_s * d64[live] / mag[live, None]
+    return np.nonzero(dynamic)[0], loss, grad
 

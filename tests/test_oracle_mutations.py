@@ -174,3 +174,17 @@ def test_adam_without_bias_correction_is_caught(monkeypatch):
         return real(p, g, m, v, lr, beta1, beta2, eps, 10 ** 9, grad_scale, lazy_row)
     monkeypatch.setattr(O, "adam_step", uncorrected)
     expect_pin_failure(Opt.test_adam_matches_torch_adam_over_three_steps)
+
+
+def test_split_taking_ties_as_dynamic_is_caught(monkeypatch):
+    from tests import test_oracle_decompose as Dec
+    real_keys = O.motion_keys
+
+    def ties_up(dp, k_percent, lam_s=1.0):   # ">= tau" instead of "> tau"
+        key = real_keys(dp)
+        n = len(key)
+        n_d = int(math.floor(k_percent / 100.0 * n))
+        dyn = np.ones(n, bool) if n_d >= n else key >= np.sort(key)[::-1][n_d]
+        return np.nonzero(dyn)[0], 0.0, np.zeros((n, 3))
+    monkeypatch.setattr(O, "decompose", ties_up)
+    expect_pin_failure(Dec.test_split_matches_brute_force_with_ties_and_nan)
