@@ -399,6 +399,54 @@ def adam_form(torch, _lib, E: int, F: int, steps: int):
             "frac_of_hbm_peak": gbps / HBM_PEAK_GBPS, "kernel": "k_adam"}
 
 
+def front_end_form(torch, _lib, synth, steps: int):
+    """The step before the path (Section 4.1) on the paper-shaped cloud of 200k
+    Gaussians: a 3D hash encoding of the positions (the 4D encoder on the t = 0 slab
+    with one temporal cell), the 32-64-64-3 decoder for the linear motion dp, and the
+    top-10% dynamic split with the static constraint and its gradient."""
+    import numpy as np
+    w = synth.PAPER_SCENE
+    n = w.n
+    rng, x = synth.scene_inputs(n, 0)
+    x[:, 3] = 0.0
+    g = _lib.h4d_grid_init(w.L, w.F, _lib.h4d_grid_schedule(w.L, *w.space), [1] * w.L, w.T)
+    table = torch.from_numpy(synth.table_init(g.E, w.F, rng, 1e-1)).cuda()
+    params = torch.from_numpy(synth.decoder_params(w.n_in, rng, out=3)).cuda()
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    m = _lib.mlp_shape(w.n_in, out=3)
+    feat = torch.empty((w.L, n, w.F), device="cuda")
+    dp = torch.empty((n, 3), device="cuda")
+    idx = torch.empty(n, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    d_dp = torch.zeros((n, 3), device="cuda")
+    wb = _lib.hash4d_decompose_workspace_bytes(n)
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def step(timed):
+        if timed:
+            ev[0].record()
+        _lib.hash4d_encode(g, _lib.F32, table, xd, n, feat, _lib.LEVEL_MAJOR)
+        _lib.deform_mlp_forward(m, _lib.F32, params, feat, n, dp, _lib.LEVEL_MAJOR, w.F)
+        if timed:
+            ev[1].record()
+        _lib.hash4d_decompose(dp, n, 10.0, 1.0, idx, cnt, None, loss, d_dp, ws, wb)
+        if timed:
+            ev[2].record()
+    for _ in range(3):
+        step(False)
+    torch.cuda.synchronize()
+    enc = split = 0.0
+    for _ in range(steps):
+        step(True)
+        torch.cuda.synchronize()
+        enc += ev[0].elapsed_time(ev[1])
+        split += ev[1].elapsed_time(ev[2])
+    return {"gaussians": n, "k_percent": 10.0, "dynamic": int(cnt.item()), "encode_decode_ms": enc / steps,
+            "split_ms": split / steps, "value": n / ((enc + split) / steps / 1e3), "unit": "Gaussians/s"}
+
+
 def traffic_record(dominant: str):
     """HBM bytes per launch of the dominant part of the step, from the committed
     rocprofv3 --pmc summary (its fenced json block), if that was taken for the current
@@ -474,7 +522,8 @@ def main():
         "gpu_ms_per_step": gpu_ms,
     }
     result["next"] = {"input_grad": input_grad_form(torch, _lib, fp32, args.steps),
-                      "adam_table": adam_form(torch, _lib, fp32.E, fp32.w.F, args.steps)}
+                      "adam_table": adam_form(torch, _lib, fp32.E, fp32.w.F, args.steps),
+                      "front_end": front_end_form(torch, _lib, synth, min(args.steps, 20))}
     del fp32
     torch.cuda.empty_cache()
     bf = Path(torch, _lib, synth, "bf16")

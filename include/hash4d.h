@@ -191,6 +191,28 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
  * BF16 form reads.  count elements; dst may not overlap src. */
 h4d_status h4d_cast_bf16(const float* src, uint16_t* dst, int64_t count, void* stream);
 
+/* ------------------------------------------- dynamic-static split ---- */
+
+/* Self-supervised split of Section 4.1 (the step before the 4D path: it decides
+ * which Gaussians the path deforms) and the static constraint of Eq. 5.
+ *   dp [n, 3] FP32: each Gaussian's linear-motion vector (Eq. 4, p(t) = p + t dp),
+ *   e.g. deform_mlp_forward with out = 3 on a 3D hash encoding of the positions.
+ * Keys are the FP32 squares s = (dx^2 + dy^2) + dz^2 (no fused multiply-add),
+ * ordered by bit pattern (NaN above +Inf).  n_d = floor(k_percent / 100 * n);
+ * the threshold is the (n_d + 1)-th largest key (none if n_d >= n) and a Gaussian
+ * is dynamic iff its key is strictly greater (ties stay static).  Outputs (each may
+ * be NULL): dynamic_idx [n] int32 gets the dynamic indices in ascending order;
+ * *n_dynamic (device int32) their count; is_dynamic [n] uint8 0/1;
+ * *loss (device FP32) += lambda_s / N_s * sum over static ||dp|| (nothing if N_s = 0);
+ * d_dp [n, 3] += its gradient lambda_s / N_s * dp / ||dp|| on static rows (0 where
+ * dp = 0).  workspace: device, 16-byte aligned, hash4d_decompose_workspace_bytes(n).
+ * The selection and the indices are exact and deterministic; the loss sums in a
+ * fixed order. */
+size_t hash4d_decompose_workspace_bytes(int64_t n);
+h4d_status hash4d_decompose(const float* dp, int64_t n, float k_percent, float lambda_s, int32_t* dynamic_idx,
+                            int32_t* n_dynamic, uint8_t* is_dynamic, float* loss, float* d_dp, void* workspace,
+                            size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------ optimiser step ---- */
 
 /* Hyper-parameters of one Adam step (host struct). */

@@ -116,6 +116,8 @@ SIGNATURES = {
     "hash4d_batched_run": (_I32, [_P, _P]),
     "hash4d_batched_plan_info": (_I32, [_P, ctypes.POINTER(BatchedInfo)]),
     "hash4d_batched_plan_destroy": (None, [_P]),
+    "hash4d_decompose_workspace_bytes": (_SZ, [_I64]),
+    "hash4d_decompose": (_I32, [_P, _I64, _F32, _F32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "h4d_adam_step": (_I32, [_P, _P, _P, _P, _I64, _I32, ctypes.POINTER(Adam), _P, _I32, _P]),
     "h4d_probe_gather": (_I32, [_P, _I64, _I32, _I64, ctypes.c_uint32, _P, _P]),
     "h4d_probe_scatter": (_I32, [_P, _I64, _I64, ctypes.c_uint32, _I32, _P]),
@@ -365,6 +367,17 @@ def h4d_probe_copy(src, dst, nbytes: int, stream=None) -> None:
 def h4d_probe_lds_atomic(blocks: int, per_thread: int, active: int, seed: int, mode: int, sink, stream=None) -> None:
     _check("h4d_probe_lds_atomic", load().h4d_probe_lds_atomic(blocks, per_thread, active, seed, mode, ptr(sink),
                                                                stream_handle(stream)))
+
+
+def hash4d_decompose_workspace_bytes(n: int) -> int:
+    return int(load().hash4d_decompose_workspace_bytes(n))
+
+
+def hash4d_decompose(dp, n: int, k_percent: float, lambda_s: float, dynamic_idx, n_dynamic, is_dynamic, loss, d_dp,
+                     workspace, ws_bytes: int, stream=None) -> None:
+    _check("hash4d_decompose", load().hash4d_decompose(ptr(dp), n, k_percent, lambda_s, ptr(dynamic_idx),
+                                                       ptr(n_dynamic), ptr(is_dynamic), ptr(loss), ptr(d_dp),
+                                                       ptr(workspace), ws_bytes, stream_handle(stream)))
 
 
 def h4d_adam_step(params, grad, m, v, count: int, lr: float, beta1: float, beta2: float, eps: float, step: int,

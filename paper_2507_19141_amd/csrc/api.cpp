@@ -350,6 +350,29 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
                       "smoothness_reg/scatter");
 }
 
+size_t hash4d_decompose_workspace_bytes(int64_t n) {
+    if (n < 0 || n > kMaxN) return 0;
+    return decompose_workspace_bytes(n);
+}
+
+h4d_status hash4d_decompose(const float* dp, int64_t n, float k_percent, float lambda_s, int32_t* dynamic_idx,
+                            int32_t* n_dynamic, uint8_t* is_dynamic, float* loss, float* d_dp, void* workspace,
+                            size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    if (n < 0 || n > kMaxN) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-1", (long long)n);
+    if (!(k_percent >= 0.f && k_percent <= 100.f)) return fail(H4D_EINVAL, "k_percent must be in [0, 100]");
+    if (n == 0) return H4D_OK;
+    if (!dp) return fail(H4D_EINVAL, "dp is NULL");
+    if ((((uintptr_t)dp) | ((uintptr_t)d_dp)) & 3u) return fail(H4D_EINVAL, "dp and d_dp must be 4-byte aligned");
+    const size_t need = decompose_workspace_bytes(n);
+    if (!workspace || ws_bytes < need)
+        return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    if (((uintptr_t)workspace) & 15u) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
+    return hip_status(launch_decompose(dp, n, (double)k_percent, lambda_s, dynamic_idx, n_dynamic, is_dynamic, loss,
+                                       d_dp, workspace, (hipStream_t)stream),
+                      "hash4d_decompose");
+}
+
 h4d_status h4d_adam_step(float* params, float* grad, float* m, float* v, int64_t count, int32_t row,
                          const h4d_adam* hp, uint16_t* bf16_out, int32_t flags, void* stream) {
     g_last_error.clear();

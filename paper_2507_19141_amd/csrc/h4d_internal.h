@@ -71,6 +71,10 @@ hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, int row, double lr, double beta1,
                        double beta2, double eps, int step, double grad_scale, uint16_t* lo, bool lazy, bool zero,
                        hipStream_t s);
+// Dynamic-static split and static constraint (decompose.hip).
+size_t decompose_workspace_bytes(int64_t n);
+hipError_t launch_decompose(const float* dp, int64_t n, double k_percent, float lam_s, int32_t* dyn_idx,
+                            int32_t* n_dynamic, uint8_t* is_dyn, float* loss, float* d_dp, void* ws, hipStream_t s);
 // d_xyzt[q] += scale * d<f_h, d_feat>/dx (encode_input.hip).
 hipError_t launch_encode_input_grad(const DevGrid& g, h4d_dtype dt, const void* table, const float* xyzt, int n,
                                     const void* d_feat, int64_t lstride, int64_t qstride, double scale, void* d_xyzt,

@@ -148,6 +148,11 @@ def test_entry_points_validate_without_launching():
     bad = _lib.Adam(1e-3, 0.9, 0.999, 1e-8, 0, 1.0)
     assert lib.h4d_adam_step(fake, fake, fake, fake, 8, 1, _lib.ctypes.byref(bad), None, 0, None) == -1  # step 0
     assert lib.h4d_adam_step(None, None, None, None, 0, 1, hpp, None, 0, None) == 0        # count 0
+    assert lib.hash4d_decompose(fake, 10, 101.0, 1.0, None, None, None, None, None, fake, 1 << 20, None) == -1  # k
+    assert lib.hash4d_decompose(None, 10, 10.0, 1.0, None, None, None, None, None, fake, 1 << 20, None) == -1  # dp
+    assert lib.hash4d_decompose(fake, 10, 10.0, 1.0, None, None, None, None, None, fake, 8, None) == -1       # ws
+    assert lib.hash4d_decompose(fake, 0, 10.0, 1.0, None, None, None, None, None, None, 0, None) == 0          # n 0
+    assert _lib.hash4d_decompose_workspace_bytes(1000) == 256 + 1024 + 12 * 4
     m = _lib.mlp_shape(32)
     mp = _lib.ctypes.byref(m)
     assert lib.deform_mlp_forward(mp, 0, fake, fake, 5, 1, 3, fake, None) == -1            # F must divide in
