@@ -59,6 +59,9 @@ Readings of points the paper leaves open (each also listed in the design doc):
      strictly greater, so ties at tau are static.  The static constraint (Eq. 5) is
      lam_s / N_s * sum over static ||dp|| (lam_s of Eq. 6 folded in), its gradient
      lam_s / N_s * dp / ||dp|| (0 where dp = 0); N_s = 0 contributes nothing.
+ R11 Collision census (the "w/o dec" ablation of Section 5.3 measures the cost of
+     hashing the whole scene): over the 16 corners of the queries at one level, V
+     distinct vertices and R distinct table rows; V - R vertices share their row.
  R8  Input gradient (the step after the path: learned canonical positions through
      the encoder): the derivative of Eq. 9 with respect to x_d in the cell the
      forward selects (lower corner min(floor(x N), N - 1)), d w_c / d x_d =
@@ -483,4 +486,20 @@ def decompose(dp, k_percent: float, lam_s: float = 1.0):
         live = static & (mag > 0)
         grad[live] = lam_s / n_s * d64[live] / mag[live, None]
     return np.nonzero(dynamic)[0], loss, grad
+
+
+# ----------------------------------------------------------------------------
+# Collision census (R11)
+# ----------------------------------------------------------------------------
+def collision_census(xyzt, grid: Grid, level: int):
+    """(V, R): distinct corner vertices and distinct table rows at one level."""
+    x32 = clamp_unit_f32(xyzt)
+    res = (grid.res_s[level],) * 3 + (grid.res_t[level],)
+    lo = [cell_position(x32[:, d], res[d])[0] for d in range(4)]
+    rows, _ = corners(xyzt, grid)
+    verts = set()
+    for c in range(16):
+        v = [lo[d] + ((c >> d) & 1) for d in range(4)]
+        verts.update(zip(*(a.tolist() for a in v)))
+    return len(verts), len(np.unique(rows[:, level, :]))
 
