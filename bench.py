@@ -63,16 +63,16 @@ def source_hash() -> str:
 class Path:
     """Device buffers and the step of one form (fp32 or bf16) of the workload."""
 
-    def __init__(self, torch, _lib, synth, form: str):
+    def __init__(self, torch, _lib, synth, form: str, n: int | None = None):
         self.torch, self.L_, self.form = torch, _lib, form
         w = synth.PAPER_SCENE
         self.w = w
-        rng, x = synth.scene_inputs(w.n, 0)
+        rng, x = synth.scene_inputs(w.n if n is None else n, 0)
         rs = _lib.h4d_grid_schedule(w.L, *w.space)
         rt = _lib.h4d_grid_schedule(w.L, *w.time)
         self.g = _lib.h4d_grid_init(w.L, w.F, rs, rt, w.T)
         self.m = _lib.mlp_shape(w.n_in)
-        E, F, n = self.g.E, w.F, w.n
+        E, F, n = self.g.E, w.F, x.shape[0]
         table = synth.table_init(E, F, rng)
         params = synth.decoder_params(w.n_in, rng)
         gd = synth.upstream(n, 10, rng)
@@ -447,6 +447,34 @@ def front_end_form(torch, _lib, synth, steps: int):
             "split_ms": split / steps, "value": n / ((enc + split) / steps / 1e3), "unit": "Gaussians/s"}
 
 
+def whole_scene_form(torch, _lib, synth, steps: int):
+    """The "w/o dec" setting: the same table (T = 2^19) hashing the whole scene, here
+    1M clustered Gaussians instead of the 200k dynamic ones.  Reports the collision
+    census (V distinct corner vertices, R distinct rows, 1 - R / V) at a middle and
+    the finest level for both sets, and the FP32 step on the whole scene."""
+    w = synth.PAPER_SCENE
+    g = _lib.h4d_grid_init(w.L, w.F, _lib.h4d_grid_schedule(w.L, *w.space), _lib.h4d_grid_schedule(w.L, *w.time),
+                           w.T)
+    out = {"census": {}}
+    for label, n in (("dynamic_200k", w.n), ("whole_1M", 1_000_000)):
+        _, x = synth.scene_inputs(n, 0)
+        xd = torch.from_numpy(x).cuda()
+        counts = torch.zeros(2, dtype=torch.int64, device="cuda")
+        out["census"][label] = {}
+        for level in (9, w.L - 1):
+            wb = _lib.hash4d_collision_workspace_bytes(g, level, n)
+            ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+            _lib.hash4d_collision_census(g, level, xd, n, counts, ws, wb)
+            V, R = (int(v) for v in counts.cpu())
+            out["census"][label][f"level{level}"] = {"V": V, "R": R, "collision_rate": 1.0 - R / V}
+            del ws
+    path = Path(torch, _lib, synth, "fp32", n=1_000_000)
+    wall, gpu_ms, per = path.run(steps, 2)
+    out["whole_scene_step"] = {"n": path.n, "value": path.n * steps / wall, "ms_per_step": wall * 1e3 / steps,
+                               "kernels_ms": per}
+    return out
+
+
 def traffic_record(dominant: str):
     """HBM bytes per launch of the dominant part of the step, from the committed
     rocprofv3 --pmc summary (its fenced json block), if that was taken for the current
@@ -524,6 +552,8 @@ def main():
     result["next"] = {"input_grad": input_grad_form(torch, _lib, fp32, args.steps),
                       "adam_table": adam_form(torch, _lib, fp32.E, fp32.w.F, args.steps),
                       "front_end": front_end_form(torch, _lib, synth, min(args.steps, 20))}
+    torch.cuda.empty_cache()
+    result["next"]["whole_scene"] = whole_scene_form(torch, _lib, synth, min(args.steps, 10))
     del fp32
     torch.cuda.empty_cache()
     bf = Path(torch, _lib, synth, "bf16")

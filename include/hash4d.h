@@ -191,6 +191,21 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
  * BF16 form reads.  count elements; dst may not overlap src. */
 h4d_status h4d_cast_bf16(const float* src, uint16_t* dst, int64_t count, void* stream);
 
+/* ----------------------------------------------- collision census ---- */
+
+/* Collision census of level `level` for n queries: counts[0] = V, the distinct
+ * corner vertices, counts[1] = R, the distinct table rows they map to (device int64
+ * [2], written).  On a dense level R = V; on a hashed level V - R vertices share
+ * their row with another: the cost of hashing more points that the paper's "w/o dec"
+ * ablation shows (Section 5.3).  Vertex ids take 16 bits per coordinate, so the
+ * level needs N_s, N_t < 65535 (H4D_EUNSUPPORTED otherwise).  workspace: device,
+ * 16-byte aligned, hash4d_collision_workspace_bytes(g, level, n) (a set of at least
+ * 32 n slots of 8 bytes and a bitmap of the level's rows).  Exact and deterministic
+ * counts; uses device atomics (instrumentation, not the training path). */
+size_t hash4d_collision_workspace_bytes(const h4d_grid* g, int32_t level, int64_t n);
+h4d_status hash4d_collision_census(const h4d_grid* g, int32_t level, const float* xyzt, int64_t n, int64_t* counts,
+                                   void* workspace, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------- dynamic-static split ---- */
 
 /* Self-supervised split of Section 4.1 (the step before the 4D path: it decides

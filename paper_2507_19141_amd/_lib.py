@@ -116,6 +116,8 @@ SIGNATURES = {
     "hash4d_batched_run": (_I32, [_P, _P]),
     "hash4d_batched_plan_info": (_I32, [_P, ctypes.POINTER(BatchedInfo)]),
     "hash4d_batched_plan_destroy": (None, [_P]),
+    "hash4d_collision_workspace_bytes": (_SZ, [_GP, _I32, _I64]),
+    "hash4d_collision_census": (_I32, [_GP, _I32, _P, _I64, _P, _P, _SZ, _P]),
     "hash4d_decompose_workspace_bytes": (_SZ, [_I64]),
     "hash4d_decompose": (_I32, [_P, _I64, _F32, _F32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "h4d_adam_step": (_I32, [_P, _P, _P, _P, _I64, _I32, ctypes.POINTER(Adam), _P, _I32, _P]),
@@ -367,6 +369,15 @@ def h4d_probe_copy(src, dst, nbytes: int, stream=None) -> None:
 def h4d_probe_lds_atomic(blocks: int, per_thread: int, active: int, seed: int, mode: int, sink, stream=None) -> None:
     _check("h4d_probe_lds_atomic", load().h4d_probe_lds_atomic(blocks, per_thread, active, seed, mode, ptr(sink),
                                                                stream_handle(stream)))
+
+
+def hash4d_collision_workspace_bytes(g: Grid, level: int, n: int) -> int:
+    return int(load().hash4d_collision_workspace_bytes(ctypes.byref(g), level, n))
+
+
+def hash4d_collision_census(g: Grid, level: int, xyzt, n: int, counts, workspace, ws_bytes: int, stream=None) -> None:
+    _check("hash4d_collision_census", load().hash4d_collision_census(ctypes.byref(g), level, ptr(xyzt), n, ptr(counts),
+                                                                     ptr(workspace), ws_bytes, stream_handle(stream)))
 
 
 def hash4d_decompose_workspace_bytes(n: int) -> int:

@@ -350,6 +350,31 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
                       "smoothness_reg/scatter");
 }
 
+size_t hash4d_collision_workspace_bytes(const h4d_grid* g, int32_t level, int64_t n) {
+    if (check_grid(g) != H4D_OK || level < 0 || level >= g->L || n < 0 || n > kMaxN) return 0;
+    return census_workspace_bytes(n, g->offset[level + 1] - g->offset[level]);
+}
+
+h4d_status hash4d_collision_census(const h4d_grid* g, int32_t level, const float* xyzt, int64_t n, int64_t* counts,
+                                   void* workspace, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    h4d_status st;
+    if ((st = check_grid(g)) || (st = check_xyzt(xyzt, n))) return st;
+    if (level < 0 || level >= g->L) return fail(H4D_EINVAL, "level %d outside 0..%d", level, g->L - 1);
+    if (g->res_s[level] >= 65535 || g->res_t[level] >= 65535)
+        return fail(H4D_EUNSUPPORTED, "vertex ids take 16 bits per coordinate: N_s, N_t must stay below 65535");
+    if (!counts) return fail(H4D_EINVAL, "counts is NULL");
+    if (((uintptr_t)counts) & 7u) return fail(H4D_EINVAL, "counts is not 8-byte aligned");
+    const int64_t rows = g->offset[level + 1] - g->offset[level];
+    const size_t need = census_workspace_bytes(n, rows);
+    if (!workspace || ws_bytes < need)
+        return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    if (((uintptr_t)workspace) & 15u) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
+    const DevGrid d = to_device(*g);
+    return hip_status(launch_census(d, level, rows, xyzt, (int)n, counts, workspace, (hipStream_t)stream),
+                      "hash4d_collision_census");
+}
+
 size_t hash4d_decompose_workspace_bytes(int64_t n) {
     if (n < 0 || n > kMaxN) return 0;
     return decompose_workspace_bytes(n);

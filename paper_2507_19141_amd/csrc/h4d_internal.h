@@ -71,6 +71,10 @@ hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, int row, double lr, double beta1,
                        double beta2, double eps, int step, double grad_scale, uint16_t* lo, bool lazy, bool zero,
                        hipStream_t s);
+// Collision census of one level (census.hip).
+size_t census_workspace_bytes(int64_t n, int64_t level_rows);
+hipError_t launch_census(const DevGrid& g, int l, int64_t level_rows, const float* xyzt, int n, int64_t* counts,
+                         void* ws, hipStream_t s);
 // Dynamic-static split and static constraint (decompose.hip).
 size_t decompose_workspace_bytes(int64_t n);
 hipError_t launch_decompose(const float* dp, int64_t n, double k_percent, float lam_s, int32_t* dyn_idx,

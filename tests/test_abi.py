@@ -153,6 +153,10 @@ def test_entry_points_validate_without_launching():
     assert lib.hash4d_decompose(fake, 10, 10.0, 1.0, None, None, None, None, None, fake, 8, None) == -1       # ws
     assert lib.hash4d_decompose(fake, 0, 10.0, 1.0, None, None, None, None, None, None, 0, None) == 0          # n 0
     assert _lib.hash4d_decompose_workspace_bytes(1000) == 256 + 1024 + 12 * 4
+    assert lib.hash4d_collision_census(gp, 9, fake, 5, fake, fake, 1 << 30, None) == -1       # level out of range
+    assert lib.hash4d_collision_census(gp, 0, fake, 5, None, fake, 1 << 30, None) == -1       # counts NULL
+    assert lib.hash4d_collision_census(gp, 0, fake, 5, fake, fake, 8, None) == -1             # workspace
+    assert _lib.hash4d_collision_workspace_bytes(g, 0, 1000) == 32768 * 8 + ((625 + 31) // 32) * 4
     m = _lib.mlp_shape(32)
     mp = _lib.ctypes.byref(m)
     assert lib.deform_mlp_forward(mp, 0, fake, fake, 5, 1, 3, fake, None) == -1            # F must divide in
