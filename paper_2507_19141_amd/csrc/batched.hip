@@ -585,7 +585,7 @@ h4d_status hash4d_batched_plan_create(h4d_batched_plan** out, const h4d_scene_de
         p->fwd.s[s].d_feat = nullptr;
         dfo += (int64_t)scenes[s].n_times * scenes[s].grid.L * scenes[s].n * scenes[s].grid.F;
     }
-    p->ws_bytes = mlp_partial_bytes(dt, m->in, m->out, p->bwd_blocks);
+    p->ws_bytes = mlp_partial_bytes(dt, m->in, m->out, p->bwd_blocks, n_scenes);
     if ((e = hipMalloc(&p->ws, std::max<size_t>(p->ws_bytes, 16))) != hipSuccess) return bail(plan_hip(e, "plan ws"));
     // schedule: default, or the fastest measured candidate
     std::vector<BRange> r = build_ranges(*p, segs, p->enc, &p->total_enc);

@@ -251,6 +251,21 @@ __device__ void fill_frags(typename Pol::FE* lds, int count, const typename Pol:
     }
 }
 
+// The backward's fragment tables of every span, built once per call into the
+// workspace (a workgroup per 256 elements and span); each backward workgroup then
+// copies its span's tables into LDS instead of rebuilding them.
+template <class Pol, int IN>
+__global__ __launch_bounds__(256) void k_mlp_frags(MlpBatch b, int out, typename Pol::FE* __restrict__ frags,
+                                                   int64_t stride) {
+    using Sh = Shape<Pol, IN>;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= Sh::ALL_FRAGS) return;
+    const typename Pol::S* __restrict__ params = static_cast<const typename Pol::S*>(b.s[blockIdx.y].params);
+    const ParamOff po(IN, out);
+    const int s = frag_source<Pol, IN>(t, out, po);
+    frags[(int64_t)blockIdx.y * stride + t] = s >= 0 ? Pol::to_frag(params[s]) : typename Pol::FE(0);
+}
+
 __device__ __forceinline__ int span_of_block(const MlpBatch& b) {
     int si = 0;
     for (int i = 1; i < b.count; ++i)
@@ -433,14 +448,17 @@ __device__ __forceinline__ void wmma(typename Pol::Acc& acc, const WOp<Pol>& a, 
 template <class Pol, int IN>
 __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int out, typename Pol::V in_scale,
                                                             typename Pol::V feat_scale,
-                                                            typename Pol::G* __restrict__ partial) {
+                                                            typename Pol::G* __restrict__ partial,
+                                                            const typename Pol::FE* __restrict__ frags,
+                                                            int64_t frag_stride) {
     using Sh = Shape<Pol, IN>;
     using V = typename Pol::V;
     using G = typename Pol::G;
     using Acc = typename Pol::Acc;
     constexpr bool kLds = !std::is_same<Pol, PolF64>::value;
     extern __shared__ __align__(16) unsigned char smem[];
-    const MlpSpan& sp = batch.s[span_of_block(batch)];
+    const int span = span_of_block(batch);
+    const MlpSpan& sp = batch.s[span];
     const typename Pol::S* __restrict__ params = static_cast<const typename Pol::S*>(sp.params);
     const ParamOff po(IN, out);
     // LDS: [fragment tables (FP32/BF16 only)][block gradient accumulator (FP32/BF16 only)][transpose buffers]
@@ -452,9 +470,12 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int 
 
     Frags<Pol, IN, kLds> fr{frag_lds, params, out, po};
     if constexpr (kLds) {
-        // the gradient accumulator doubles as the staging buffer of the parameters
-        fill_frags<Pol, IN>(frag_lds, Sh::ALL_FRAGS, params, out, po, reinterpret_cast<typename Pol::S*>(wacc));
-        __syncthreads();
+        // the span's tables, prepared by k_mlp_frags, copied 16 bytes per lane
+        const uint4* src = reinterpret_cast<const uint4*>(frags + (int64_t)span * frag_stride);
+        uint4* dst = reinterpret_cast<uint4*>(frag_lds);
+        constexpr int kVec = (int)(Sh::ALL_FRAGS * sizeof(typename Pol::FE) / 16);
+        static_assert(Sh::ALL_FRAGS * sizeof(typename Pol::FE) % 16 == 0, "tables are whole 16-byte vectors");
+        for (int t = threadIdx.x; t < kVec; t += blockDim.x) dst[t] = src[t];
         for (int t = threadIdx.x; t < po.P; t += blockDim.x) wacc[t] = G(0);
     }
     __syncthreads();
@@ -759,7 +780,7 @@ static size_t lds_backward(int out) {
 }
 
 size_t mlp_workspace_bytes(h4d_dtype dt, int in, int out, int n) {
-    return mlp_partial_bytes(dt, in, out, mlp_blocks_for(dt, true, n));
+    return mlp_partial_bytes(dt, in, out, mlp_blocks_for(dt, true, n), 1);
 }
 
 template <class Pol, int IN>
@@ -774,6 +795,29 @@ static hipError_t forward_t(const MlpBatch& b, int blocks, int out, hipStream_t 
     return hipGetLastError();
 }
 
+static size_t align_up(size_t b) { return (b + 255) / 256 * 256; }
+
+template <class Pol>
+static size_t partial_rows_bytes(int in, int out, int blocks) {
+    const ParamOff po(in, out);
+    return (size_t)blocks * (std::is_same<Pol, PolF64>::value ? kWaves : 1) * po.P * sizeof(typename Pol::G);
+}
+
+template <class Pol, int IN>
+static size_t frag_table_bytes() {
+    return align_up((size_t)Shape<Pol, IN>::ALL_FRAGS * sizeof(typename Pol::FE));
+}
+
+template <class Pol>
+static size_t frag_table_bytes_for(int in) {
+    switch (in) {
+        case 8: return frag_table_bytes<Pol, 8>();
+        case 16: return frag_table_bytes<Pol, 16>();
+        case 32: return frag_table_bytes<Pol, 32>();
+        default: return frag_table_bytes<Pol, 64>();
+    }
+}
+
 template <class Pol, int IN>
 static hipError_t backward_t(const MlpBatch& b, int blocks, int out, double in_scale, double feat_scale,
                              double param_scale, void* ws, hipStream_t s) {
@@ -783,8 +827,18 @@ static hipError_t backward_t(const MlpBatch& b, int blocks, int out, double in_s
     if (e != hipSuccess) return e;
     using V = typename Pol::V;
     using G = typename Pol::G;
+    using FE = typename Pol::FE;
+    using Sh = Shape<Pol, IN>;
+    // workspace: [per-block partial rows | per-span fragment tables (FP32/BF16)]
+    FE* frags = nullptr;
+    const int64_t stride = (int64_t)(frag_table_bytes<Pol, IN>() / sizeof(FE));
+    if constexpr (!std::is_same<Pol, PolF64>::value) {
+        frags = reinterpret_cast<FE*>(static_cast<char*>(ws) + align_up(partial_rows_bytes<Pol>(IN, out, blocks)));
+        hipLaunchKernelGGL((k_mlp_frags<Pol, IN>), dim3((Sh::ALL_FRAGS + 255) / 256, b.count), dim3(256), 0, s, b,
+                           out, frags, stride);
+    }
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kMlpBlock), lds, s, b, out, (V)in_scale, (V)feat_scale,
-                       static_cast<G*>(ws));
+                       static_cast<G*>(ws), frags, stride);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const ParamOff po(IN, out);
     const int rows_per_block = std::is_same<Pol, PolF64>::value ? kWaves : 1;
@@ -824,9 +878,12 @@ int mlp_blocks_for(h4d_dtype dt, bool backward, int64_t queries) {
     return mlp_blocks((int)(queries < 2147483647 ? queries : 2147483647), cap);
 }
 
-size_t mlp_partial_bytes(h4d_dtype dt, int in, int out, int blocks) {
-    const ParamOff po(in, out);
-    return (size_t)blocks * (dt == H4D_F64 ? kWaves : 1) * po.P * (dt == H4D_F64 ? sizeof(double) : sizeof(float));
+size_t mlp_partial_bytes(h4d_dtype dt, int in, int out, int blocks, int spans) {
+    switch (dt) {
+        case H4D_F32: return align_up(partial_rows_bytes<PolF32>(in, out, blocks)) + spans * frag_table_bytes_for<PolF32>(in);
+        case H4D_BF16: return align_up(partial_rows_bytes<PolBF16>(in, out, blocks)) + spans * frag_table_bytes_for<PolBF16>(in);
+        default: return partial_rows_bytes<PolF64>(in, out, blocks);
+    }
 }
 
 static MlpBatch single(const void* params, const void* feat, void* delta, const void* d_out, void* d_feat,
