@@ -663,10 +663,13 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int 
         for (int idx = 0; idx < Sh::NO; ++idx) sb3[idx] += __shfl_xor(sb3[idx], s, 64);
     }
 
-    // Emit the wavefront partial gradients.  FP32/BF16: the wavefronts add theirs to
-    // the block accumulator in LDS one after another (plain read-modify-write; every
-    // lane of an emit touches a different parameter), so the block sum has a fixed
-    // order.  FP64: each wavefront writes its own workspace row.
+    // Emit the wavefront partial gradients.  FP32/BF16: the parameters fall into four
+    // blocks (row tiles mo of W1 and W2, column tiles nt of W3, quarters of b1 and b2;
+    // b3 joins block 0), and in round r wavefront w adds its block (w + r) mod 4 to
+    // the block accumulator in LDS with plain read-modify-writes.  The four
+    // wavefronts work on disjoint blocks at once, and every parameter receives the
+    // wavefronts' sums in a fixed order.  FP64: each wavefront writes its own row.
+    static_assert(!kLds || kWaves == 4, "one parameter block per wavefront");
     const int wave = threadIdx.x >> 6;
     G* dst = kLds ? wacc : partial + (size_t)(blockIdx.x * kWaves + wave) * po.P;
     auto emit = [&](int p, G v) {
@@ -674,23 +677,25 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int 
         else dst[p] = v;
     };
     for (int round = 0; round < (kLds ? kWaves : 1); ++round) {
-        if (!kLds || wave == round) {
+        const int blk = (wave + round) & 3;
+        auto mine = [&](int b) { return !kLds || b == blk; };
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
+        for (int nt = 0; nt < 4; ++nt)
+            if (mine(nt)) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int o = 4 * kb + r;
                     if (o < out) emit(po.W3 + o * HID + 16 * nt + j, (G)Pol::get(w3[nt], r));
                 }
+            }
 #pragma unroll
-            for (int mo = 0; mo < 4; ++mo)
+        for (int mo = 0; mo < 4; ++mo)
+            if (mine(mo)) {
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
                         emit(po.W2 + (16 * mo + 4 * kb + r) * HID + 16 * nt + j, (G)Pol::get(w2[mo][nt], r));
-#pragma unroll
-            for (int mo = 0; mo < 4; ++mo)
 #pragma unroll
                 for (int nf = 0; nf < Sh::MF; ++nf)
 #pragma unroll
@@ -698,12 +703,15 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int 
                         const int f = 16 * nf + j;
                         if (f < IN) emit(po.W1 + (16 * mo + 4 * kb + r) * IN + f, (G)Pol::get(w1[mo][nf], r));
                     }
-            if (j == 0) {
+            }
+        if (j == 0) {
 #pragma unroll
-                for (int idx = 0; idx < 16; ++idx) {
+            for (int idx = 0; idx < 16; ++idx)
+                if (mine(idx >> 2)) {
                     emit(po.b1 + hid(idx, kb), (G)sb1[idx]);
                     emit(po.b2 + hid(idx, kb), (G)sb2[idx]);
                 }
+            if (mine(0)) {
 #pragma unroll
                 for (int idx = 0; idx < Sh::NO; ++idx) {
                     const int o = kb * Sh::NO + idx;
