@@ -133,8 +133,8 @@ h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* tabl
  * sums its rows' updates in LDS and adds them to d_table; no device-wide atomics.
  * A pre-pass writes a per-(query, level) mask of touched tiles into `workspace`
  * (device, at least hash4d_encode_backward_workspace_bytes) so that each tile only
- * works on the queries that reach it.  LDS atomics make the summation order, hence
- * the last bits, vary run to run. */
+ * works on the queries that reach it.  The LDS adds (compare-and-swap, one FP32
+ * rounding each) make the summation order, hence the last bits, vary run to run. */
 size_t hash4d_encode_backward_workspace_bytes(const h4d_grid* g, int64_t n);
 h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
                                   h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,

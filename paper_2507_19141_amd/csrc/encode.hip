@@ -80,17 +80,18 @@ __global__ __launch_bounds__(kEncodeBlock) void k_encode(DevGrid g, const TT* __
 // Device-scope FP32 atomics on MI355X complete at a fixed rate of about 2e10 per
 // second whatever the footprint (they are not executed in the XCD-local L2), so
 // the scatter avoids them altogether.  Owner computes: one workgroup per (level,
-// tile of R consecutive table rows of that level) keeps the tile's gradient in LDS,
-// adds w_c g for the corners of the level's queries that fall in its tile with LDS
-// atomics, and finally adds the tile to d_table with plain loads and stores (no
-// other workgroup owns those rows).
+// tile of 2^tile_shift consecutive table rows of that level; about 32 tiles per
+// level) keeps the tile's gradient in LDS, adds w_c g for the corners of the
+// level's queries that fall in its tile with compare-and-swap LDS adds (lds_add2),
+// and finally adds the tile to d_table with plain loads and stores (no other
+// workgroup owns those rows).
 //
 // A pre-pass records, per (query, level), a 32-bit mask of the tiles the query's
-// corners touch (tile t of a level with P tiles sets bit t*32/P).  A tile
-// workgroup reads the masks of its level, compacts the queries whose bit is set
-// into an LDS queue and runs the corner work on full wavefronts of those queries
-// only.  With pi_1 = 1 the two x-corners of a hashed level share a tile, so a
-// query touches at most 8 of a hashed level's tiles.
+// corners touch (tile t sets bit t >> bit_shift).  A tile workgroup reads the
+// masks of its level, compacts the queries whose bit is set into per-wavefront LDS
+// queues and runs the corner work on full wavefronts of those queries only.  With
+// pi_1 = 1 the two x-corners of a hashed level share a tile, so a query touches at
+// most 8 of a hashed level's tiles.
 // PAIR: each query also subtracts the same gradient at the corners of x + eps (the
 // second term of Eq. 11).
 
