@@ -234,20 +234,23 @@ struct Frags {
 
 template <class Pol, int IN>
 __device__ void fill_frags(typename Pol::FE* lds, int count, const typename Pol::S* __restrict__ params, int out,
-                           const ParamOff& po, typename Pol::S* stage) {
-    // With a staging buffer: one coalesced burst of the parameters into LDS first (many
-    // loads in flight), then the fragment permutation reads LDS only.  Without one: the
-    // permutation reads the (L2-resident) parameters directly.
-    const typename Pol::S* src = params;
-    if (stage) {
-#pragma unroll 8
-        for (int i = threadIdx.x; i < po.P; i += blockDim.x) stage[i] = params[i];
-        __syncthreads();
-        src = stage;
-    }
-    for (int t = threadIdx.x; t < count; t += blockDim.x) {
-        const int s = frag_source<Pol, IN>(t, out, po);
-        lds[t] = s >= 0 ? Pol::to_frag(src[s]) : typename Pol::FE(0);
+                           const ParamOff& po) {
+    // The permutation reads the (L2-resident) parameters directly, eight independent
+    // loads in flight per thread before their LDS stores.
+    constexpr int B = 8;
+    for (int t0 = threadIdx.x; t0 < count; t0 += B * blockDim.x) {
+        typename Pol::FE v[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int t = t0 + k * (int)blockDim.x;
+            const int s = t < count ? frag_source<Pol, IN>(t, out, po) : -1;
+            v[k] = s >= 0 ? Pol::to_frag(params[s]) : typename Pol::FE(0);
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int t = t0 + k * (int)blockDim.x;
+            if (t < count) lds[t] = v[k];
+        }
     }
 }
 
@@ -361,7 +364,7 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(MlpBatch batch, int o
     const ParamOff po(IN, out);
     Frags<Pol, IN, kLds> fr{reinterpret_cast<const typename Pol::FE*>(smem), params, out, po};
     if constexpr (kLds)  // no staging buffer: the forward keeps its LDS small for occupancy
-        fill_frags<Pol, IN>(reinterpret_cast<typename Pol::FE*>(smem), Sh::FWD_FRAGS, params, out, po, nullptr);
+        fill_frags<Pol, IN>(reinterpret_cast<typename Pol::FE*>(smem), Sh::FWD_FRAGS, params, out, po);
     __syncthreads();
     V b1[16], b2[16], b3[4];
     load_biases<Pol>(params, po, out, b1, b2, b3);
