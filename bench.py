@@ -31,7 +31,8 @@ HBM_PEAK_GBPS = 8000.0
 KERNEL_SOURCES = ("encode.hip", "h4d_device.h", "h4d_internal.h", "mlp.hip")
 # the library kernels behind each timed part of the step
 STEP_KERNELS = {"cast": ["k_cast_bf16"], "encode": ["k_encode"], "decode": ["k_mlp_forward"],
-                "decode_bwd": ["k_mlp_backward", "k_mlp_reduce"], "scatter": ["k_tile_mask", "k_scatter_tiled"]}
+                "decode_bwd": ["k_mlp_frags", "k_mlp_backward", "k_mlp_reduce"],
+                "scatter": ["k_tile_mask", "k_scatter_tiled"]}
 TRAFFIC_FILE = os.path.join("profiles", "traffic_deform_paper_scene_fp32.md")
 
 
@@ -43,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-probes", action="store_true", help="skip the roofline probes")
     ap.add_argument("--no-batched", action="store_true", help="skip the multi-scene form")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the steps beyond the path (input gradient, optimiser, front end, whole scene)")
     ap.add_argument("--counters", action="store_true",
                     help="a few FP32 steps plus one 256 MiB copy kernel (the calibration reference of the "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE passes); prints the step kernels' names")
@@ -549,11 +552,12 @@ def main():
         "kernels_ms": per,
         "gpu_ms_per_step": gpu_ms,
     }
-    result["next"] = {"input_grad": input_grad_form(torch, _lib, fp32, args.steps),
-                      "adam_table": adam_form(torch, _lib, fp32.E, fp32.w.F, args.steps),
-                      "front_end": front_end_form(torch, _lib, synth, min(args.steps, 20))}
-    torch.cuda.empty_cache()
-    result["next"]["whole_scene"] = whole_scene_form(torch, _lib, synth, min(args.steps, 10))
+    if not args.no_next:
+        result["next"] = {"input_grad": input_grad_form(torch, _lib, fp32, args.steps),
+                          "adam_table": adam_form(torch, _lib, fp32.E, fp32.w.F, args.steps),
+                          "front_end": front_end_form(torch, _lib, synth, min(args.steps, 20))}
+        torch.cuda.empty_cache()
+        result["next"]["whole_scene"] = whole_scene_form(torch, _lib, synth, min(args.steps, 10))
     del fp32
     torch.cuda.empty_cache()
     bf = Path(torch, _lib, synth, "bf16")
