@@ -354,6 +354,30 @@ def batched_form(torch, _lib, synth, steps: int, warmup: int):
             "unbatched_ms_per_step": u_wall * 1e3 / u_steps}
 
 
+def smoothness_form(torch, _lib, synth, path, steps: int):
+    """Eq. 11 on the paper scene: loss and table gradient for the 200k queries and
+    their perturbed copies (sigma = 1e-3), FP32 table, timed on its own."""
+    import numpy as np
+    n = path.n
+    eps = torch.from_numpy(synth.perturbation(n, np.random.default_rng(5))).cuda()
+    loss = torch.zeros(1, device="cuda")
+    wb = _lib.smoothness_workspace_bytes(path.g, _lib.F32, n)
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    call = lambda: _lib.smoothness_reg(path.g, _lib.F32, path.table32, path.xyzt, eps, n, 1.0, loss, path.d_table,
+                                       ws, wb)
+    for _ in range(3):
+        call()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        call()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    return {"ms": ms, "value": n / (ms / 1e3), "unit": "queries/s", "lambda": 1.0, "sigma": 1e-3,
+            "kernels": ["k_smooth", "k_tile_mask", "k_scatter_tiled"]}
+
+
 def input_grad_form(torch, _lib, path, steps: int):
     """The next step beyond the path: the encoder's gradient with respect to the
     positions (table FP32, level-major upstream gradients of the last step), timed
@@ -558,12 +582,14 @@ def main():
                           "front_end": front_end_form(torch, _lib, synth, min(args.steps, 20))}
         torch.cuda.empty_cache()
         result["next"]["whole_scene"] = whole_scene_form(torch, _lib, synth, min(args.steps, 10))
+    smooth = smoothness_form(torch, _lib, synth, fp32, args.steps)
     del fp32
     torch.cuda.empty_cache()
     bf = Path(torch, _lib, synth, "bf16")
     wall_b, gpu_b, per_b = bf.run(args.steps, args.warmup)
     result["forms"] = {"bf16": {"value": n * args.steps / wall_b, "ms_per_step": wall_b * 1e3 / args.steps,
-                                "kernels_ms": per_b, "loss_scale": bf.loss_scale}}
+                                "kernels_ms": per_b, "loss_scale": bf.loss_scale},
+                       "smoothness": smooth}
     del bf
     torch.cuda.empty_cache()
     if not args.no_batched:
