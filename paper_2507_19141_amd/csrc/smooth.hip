@@ -3,15 +3,50 @@
 // and, when asked, the per-(query, level) difference d = G(x) - G(x~) written
 // level-major for the table-gradient pass (the tiled scatter with the pair of
 // corner sets, scaled by 2 lam / n).  Both encodes are recomputed per (query,
-// level); when x and x~ fall in the same hypervoxel their 16 corners coincide and
-// one gather per corner gives d with the weight difference w - w~.
+// level); when x and x~ fall in the same hypervoxel (the coarse levels for a small
+// eps) their 16 corners coincide and one gather per corner gives d with the weight
+// difference w - w~.  Work items (level, 256 queries) are placed on XCDs level by
+// level, and F = 2 FP32 / BF16 tables aligned to two rows read an x-pair of corners
+// that shares an aligned row pair with one load, both as in the encoder.
 #include "h4d_device.h"
 
 namespace h4d {
 
 constexpr int kSmoothBlock = 256;
 
-template <typename TT, int F>
+// The 16 corner rows of one cell into v; PAIRS as in the encoder's forward.
+template <typename TT, int F, bool PAIRS, typename A>
+__device__ __forceinline__ void gather_corners(const DevGrid& g, const TT* __restrict__ table,
+                                               const uint32_t (&row)[16], A (&v)[16][F]) {
+    if constexpr (PAIRS) {
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t r0 = row[2 * p], r1 = row[2 * p + 1];
+            const uint32_t a = r0 & ~1u;
+            if (a + 1u < g.rows) {
+                A lo[2], hi[2];
+                RowPairLoad<TT, A>::load(table, a, lo, hi);
+                const bool odd = r0 & 1u;
+#pragma unroll
+                for (int f = 0; f < 2; ++f) v[2 * p][f] = odd ? hi[f] : lo[f];
+                if (r1 == (r0 ^ 1u)) {
+#pragma unroll
+                    for (int f = 0; f < 2; ++f) v[2 * p + 1][f] = odd ? lo[f] : hi[f];
+                } else {
+                    RowLoad<TT, F, A>::load(table, r1, v[2 * p + 1]);
+                }
+            } else {
+                RowLoad<TT, F, A>::load(table, r0, v[2 * p]);
+                RowLoad<TT, F, A>::load(table, r1, v[2 * p + 1]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) RowLoad<TT, F, A>::load(table, row[k], v[k]);
+    }
+}
+
+template <typename TT, int F, bool PAIRS>
 __global__ __launch_bounds__(kSmoothBlock) void k_smooth(DevGrid g, const TT* __restrict__ table,
                                                          const float4* __restrict__ xyzt,
                                                          const float4* __restrict__ eps, int n,
@@ -20,8 +55,10 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth(DevGrid g, const TT* __
                                                          typename AccOf<TT>::type* __restrict__ d_out) {
     using A = typename AccOf<TT>::type;
     __shared__ A red[kSmoothBlock / 64];
-    const int l = blockIdx.y;
-    const int q = blockIdx.x * kSmoothBlock + threadIdx.x;
+    const int chunks = (n + kSmoothBlock - 1) / kSmoothBlock;
+    int l, chunk;
+    if (!xcd_item(g.L * chunks, chunks, l, chunk)) return;
+    const int q = chunk * kSmoothBlock + threadIdx.x;
     A part = A(0);
     if (q < n) {
         const float4 x = xyzt[q];
@@ -40,21 +77,18 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth(DevGrid g, const TT* __
 #pragma unroll
         for (int f = 0; f < F; ++f) d[f] = A(0);
         if (same) {
+            A v[16][F];
+            gather_corners<TT, F, PAIRS>(g, table, r0, v);
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                A v[F];
-                RowLoad<TT, F, A>::load(table, r0[k], v);
                 const A dw = w0[k] - w1[k];
 #pragma unroll
-                for (int f = 0; f < F; ++f) d[f] += dw * v[f];
+                for (int f = 0; f < F; ++f) d[f] += dw * v[k][f];
             }
         } else {
             A v0[16][F], v1[16][F];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                RowLoad<TT, F, A>::load(table, r0[k], v0[k]);
-                RowLoad<TT, F, A>::load(table, r1[k], v1[k]);
-            }
+            gather_corners<TT, F, PAIRS>(g, table, r0, v0);
+            gather_corners<TT, F, PAIRS>(g, table, r1, v1);
             A a0[F], a1[F];
 #pragma unroll
             for (int f = 0; f < F; ++f) a0[f] = a1[f] = A(0);
@@ -91,18 +125,26 @@ template <typename TT>
 static hipError_t smooth_t(const DevGrid& g, const void* table, const float* xyzt, const float* eps, int n, double lam,
                            void* loss, void* d_out, hipStream_t s) {
     using A = typename AccOf<TT>::type;
-    const dim3 grid((unsigned)((n + kSmoothBlock - 1) / kSmoothBlock), (unsigned)g.L), block(kSmoothBlock);
+    const int chunks = (n + kSmoothBlock - 1) / kSmoothBlock;
+    const dim3 grid((unsigned)(kXcds * xcd_items_per(g.L * chunks))), block(kSmoothBlock);
     const TT* t = static_cast<const TT*>(table);
     const float4* x = reinterpret_cast<const float4*>(xyzt);
     const float4* e = reinterpret_cast<const float4*>(eps);
     const A c = (A)(lam / (double)n);
     A* lo = static_cast<A*>(loss);
     A* dd = static_cast<A*>(d_out);
+    constexpr bool kPairable = !std::is_same<TT, double>::value;
+    const bool pairs = kPairable && ((uintptr_t)table % (2 * 2 * sizeof(TT))) == 0;
     switch (g.F) {
-        case 1: hipLaunchKernelGGL((k_smooth<TT, 1>), grid, block, 0, s, g, t, x, e, n, c, lo, dd); break;
-        case 2: hipLaunchKernelGGL((k_smooth<TT, 2>), grid, block, 0, s, g, t, x, e, n, c, lo, dd); break;
-        case 4: hipLaunchKernelGGL((k_smooth<TT, 4>), grid, block, 0, s, g, t, x, e, n, c, lo, dd); break;
-        case 8: hipLaunchKernelGGL((k_smooth<TT, 8>), grid, block, 0, s, g, t, x, e, n, c, lo, dd); break;
+        case 1: hipLaunchKernelGGL((k_smooth<TT, 1, false>), grid, block, 0, s, g, t, x, e, n, c, lo, dd); break;
+        case 2:
+            if (pairs)
+                hipLaunchKernelGGL((k_smooth<TT, 2, kPairable>), grid, block, 0, s, g, t, x, e, n, c, lo, dd);
+            else
+                hipLaunchKernelGGL((k_smooth<TT, 2, false>), grid, block, 0, s, g, t, x, e, n, c, lo, dd);
+            break;
+        case 4: hipLaunchKernelGGL((k_smooth<TT, 4, false>), grid, block, 0, s, g, t, x, e, n, c, lo, dd); break;
+        case 8: hipLaunchKernelGGL((k_smooth<TT, 8, false>), grid, block, 0, s, g, t, x, e, n, c, lo, dd); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
