@@ -112,8 +112,7 @@ class Path:
             if ev is not None:
                 ev[k].record()
             k += 1
-        self.d_table.zero_()
-        self.d_params.zero_()
+        # both backward calls write their gradient outputs (no separate zeroing pass)
         mark()
         if self.form == "bf16":
             # precision glue: BF16 copies of the FP32 masters, loss-scaled backward, overflow count
@@ -129,10 +128,10 @@ class Path:
         L_.deform_mlp_forward(self.m, self.dt, params, self.feat, self.n, self.delta, LM, F)
         mark()
         L_.deform_mlp_backward(self.m, self.dt, params, self.feat, self.n, self.d_delta, S, 1.0 / S, self.d_feat,
-                               self.d_params, self.ws, self.ws_bytes, LM, F)
+                               self.d_params, self.ws, self.ws_bytes, LM | L_.GRAD_OVERWRITE, F)
         mark()
         L_.hash4d_encode_backward(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0 / S, self.d_table, self.sws,
-                                  self.sws_bytes, LM)
+                                  self.sws_bytes, LM | L_.GRAD_OVERWRITE)
         if self.form == "bf16":
             L_.h4d_count_nonfinite(self.d_table, self.E * F, self.counter)
             L_.h4d_count_nonfinite(self.d_params, self.d_params.numel(), self.counter)

@@ -56,6 +56,11 @@ typedef enum {
     H4D_LEVEL_MAJOR = 1   /* features [L, n, F]: at l n F + q F + f (coalesced per level) */
 } h4d_layout;
 
+/* Or-ed into the layout argument of hash4d_encode_backward and deform_mlp_backward:
+ * the gradient output (d_table, d_params) is WRITTEN, every element, instead of
+ * accumulated, so the caller need not zero it first (n = 0 writes zeros). */
+#define H4D_GRAD_OVERWRITE 0x100
+
 typedef enum {
     H4D_SCHEDULE_GEOMETRIC = 0, /* Eq. 7: N_l = floor(N_min b^l), b = (N_max/N_min)^(1/(L-1)) */
     H4D_SCHEDULE_DOUBLING = 1   /* N_l = min(N_min 2^l, N_max) */
@@ -128,7 +133,8 @@ h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* tabl
  * interpolation in Eq. 9): d_table[row_c, f] += grad_scale * w_c * d_feat[q, l F + f]
  * over every query, level and corner.  Corners and weights are recomputed from
  * xyzt.  grad_dt F32: d_feat and d_table are FP32; F64: both FP64.
- *   d_feat  n L F values in `layout`     d_table [E, F] (+=)
+ *   d_feat  n L F values in `layout`     d_table [E, F] (+=; = with H4D_GRAD_OVERWRITE
+ *           in layout, which writes every row, zeros where no corner lands)
  * Owner-computes scatter: one workgroup per (level, tile of consecutive table rows)
  * sums its rows' updates in LDS and adds them to d_table; no device-wide atomics.
  * A pre-pass writes a per-(query, level) mask of touched tiles into `workspace`
@@ -278,7 +284,8 @@ h4d_status deform_mlp_forward(const h4d_mlp* m, h4d_dtype dt, const void* params
 
 /* Decoder backward: gradients of <delta, loss_scale * d_out> (ReLU passes gradient
  * where its input is > 0).  d_feat [n, in] is WRITTEN as grad_scale times the
- * feature gradient; d_params (FP32, FP64 for F64) ACCUMULATES grad_scale times the
+ * feature gradient; d_params (FP32, FP64 for F64) ACCUMULATES (with H4D_GRAD_OVERWRITE
+ * in layout: is written with) grad_scale times the
  * parameter gradient.  The forward is recomputed from feat; weight gradients are
  * reduced over queries per persistent block into `workspace` (device, at least
  * deform_mlp_workspace_bytes) and then summed by a second kernel, so the result is

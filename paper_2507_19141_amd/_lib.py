@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhash4d.so")
 MAX_LEVELS = 32
 F32, BF16, F64 = 0, 1, 2
 QUERY_MAJOR, LEVEL_MAJOR = 0, 1
+GRAD_OVERWRITE = 0x100  # or-ed into a backward's layout: the gradient output is written, not accumulated
 SCHEDULE_GEOMETRIC, SCHEDULE_DOUBLING = 0, 1
 STATUS = {0: "H4D_OK", -1: "H4D_EINVAL", -2: "H4D_EUNSUPPORTED", -3: "H4D_EHIP", -4: "H4D_ENOPLAN"}
 

@@ -256,10 +256,17 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
     g_last_error.clear();
     h4d_status st;
     int64_t ls, qs;
+    const bool overwrite = (layout & H4D_GRAD_OVERWRITE) != 0;
+    layout = (h4d_layout)(layout & ~H4D_GRAD_OVERWRITE);
     if ((st = check_grid(g)) || (st = check_xyzt(xyzt, n))) return st;
     if (grad_dt != H4D_F32 && grad_dt != H4D_F64) return fail(H4D_EINVAL, "grad dtype must be F32 or F64");
     if ((st = feat_strides(layout, n, g->L, g->F, &ls, &qs))) return st;
-    if (n == 0) return H4D_OK;
+    if (n == 0 && !overwrite) return H4D_OK;
+    if (n == 0) {  // no query: the written gradient is zero
+        if (!d_table) return fail(H4D_EINVAL, "d_table is NULL");
+        const int64_t words = g->offset[g->L] * g->F * (grad_dt == H4D_F64 ? 2 : 1);
+        return hip_status(launch_zero_words(d_table, words, (hipStream_t)stream), "hash4d_encode_backward");
+    }
     if (!d_feat || !d_table) return fail(H4D_EINVAL, "d_feat or d_table is NULL");
     const size_t need = scatter_mask_bytes((int)n, g->L);
     if (!workspace || ws_bytes < need)
@@ -269,7 +276,7 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
     int64_t rows[H4D_MAX_LEVELS];
     rows_of(*g, rows);
     return hip_status(launch_scatter_tiled(d, rows, grad_dt, xyzt, nullptr, (int)n, d_feat, ls, qs,
-                                           (double)grad_scale, d_table, workspace, (hipStream_t)stream),
+                                           (double)grad_scale, d_table, workspace, (hipStream_t)stream, overwrite),
                       "hash4d_encode_backward");
 }
 
@@ -527,8 +534,16 @@ h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* param
     h4d_status st;
     int Fk;
     int64_t ls, qs;
+    const bool overwrite = (layout & H4D_GRAD_OVERWRITE) != 0;
+    layout = (h4d_layout)(layout & ~H4D_GRAD_OVERWRITE);
     if ((st = check_mlp(m, dt)) || (st = mlp_strides(m, n, layout, F, &Fk, &ls, &qs))) return st;
-    if (n == 0) return H4D_OK;
+    if (n == 0 && !overwrite) return H4D_OK;
+    if (n == 0) {  // no query: the written parameter gradient is zero
+        if (!d_params) return fail(H4D_EINVAL, "d_params is NULL");
+        const int64_t H = H4D_HIDDEN, P = H * m->in + H + H * H + H + (int64_t)m->out * H + m->out;
+        return hip_status(launch_zero_words(d_params, P * (dt == H4D_F64 ? 2 : 1), (hipStream_t)stream),
+                          "deform_mlp_backward");
+    }
     if (!params || !feat || !d_out || !d_feat || !d_params) return fail(H4D_EINVAL, "NULL data pointer");
     const size_t need = mlp_workspace_bytes(dt, m->in, m->out, (int)n);
     if (!workspace || ws_bytes < need)
@@ -536,7 +551,7 @@ h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* param
     if (((uintptr_t)workspace) & 15u) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
     return hip_status(launch_mlp_backward(dt, m->in, m->out, params, feat, Fk, ls, qs, (int)n, d_out, loss_scale,
                                           grad_scale, grad_scale, d_feat, ls, qs, d_params, workspace,
-                                          (hipStream_t)stream),
+                                          (hipStream_t)stream, overwrite),
                       "deform_mlp_backward");
 }
 

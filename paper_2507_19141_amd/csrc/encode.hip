@@ -162,7 +162,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
                                                                 const float4* __restrict__ eps, int n,
                                                                 const uint32_t* __restrict__ mask,
                                                                 const G* __restrict__ src, int64_t lstride,
-                                                                int64_t qstride, G scale, G* __restrict__ d_table) {
+                                                                int64_t qstride, G scale, G* __restrict__ d_table,
+                                                                int overwrite) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int queue[kQueueCap];
     G* tile = reinterpret_cast<G*>(smem);
@@ -180,10 +181,16 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
         [&](int q) { return tile_load<G, F, PAIR>(l, xyzt, eps, src, lstride, qstride, q); },
         [&](const TileQuery<G, F, PAIR>& t) { tile_run<G, F, PAIR>(g, tm, l, t, scale, base, cnt, tile); });
     __syncthreads();
+    // the tile's rows have no other owner: add them to d_table, or with overwrite set
+    // write every row (the tiles of the levels cover all E rows)
     G* out = d_table + (size_t)base * F;
-    for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) {
-        const G v = tile[i];
-        if (v != G(0)) out[i] += v;
+    if (overwrite) {
+        for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) out[i] = tile[i];
+    } else {
+        for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) {
+            const G v = tile[i];
+            if (v != G(0)) out[i] += v;
+        }
     }
 }
 
@@ -272,21 +279,21 @@ size_t scatter_mask_bytes(int n, int L) { return (size_t)mask_stride(n) * L * si
 template <typename G, int F, bool PAIR>
 static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt, const float* eps, int n,
                           const uint32_t* mask, const void* src, int64_t ls, int64_t qs, double scale, void* d_table,
-                          hipStream_t s) {
+                          bool overwrite, hipStream_t s) {
     auto kern = k_scatter_tiled<G, F, PAIR>;
     const size_t lds = (size_t)tm.max_rows * F * sizeof(G);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(tm.tile_start[g.L]), dim3(kScatterBlock), lds, s, g, tm,
                        reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n, mask,
-                       static_cast<const G*>(src), ls, qs, (G)scale, static_cast<G*>(d_table));
+                       static_cast<const G*>(src), ls, qs, (G)scale, static_cast<G*>(d_table), overwrite ? 1 : 0);
     return hipGetLastError();
 }
 
 template <typename G, bool PAIR>
 static hipError_t tiled_g(const DevGrid& g, const int64_t* level_rows, const float* xyzt, const float* eps, int n,
                           const void* src, int64_t ls, int64_t qs, double scale, void* d_table, void* mask_ws,
-                          hipStream_t s) {
+                          bool overwrite, hipStream_t s) {
     const TileMap tm = make_tile_map(g, level_rows, g.F, (int)sizeof(G));
     uint32_t* mask = static_cast<uint32_t*>(mask_ws);
     hipLaunchKernelGGL(k_tile_mask<PAIR>, dim3((unsigned)((n + kEncodeBlock - 1) / kEncodeBlock), (unsigned)g.L),
@@ -295,23 +302,26 @@ static hipError_t tiled_g(const DevGrid& g, const int64_t* level_rows, const flo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (g.F) {
-        case 1: return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, s);
-        case 2: return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, s);
-        case 4: return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, s);
-        case 8: return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, s);
+        case 1: return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, s);
+        case 2: return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, s);
+        case 4: return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, s);
+        case 8: return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d_dtype grad_dt, const float* xyzt,
                                 const float* eps, int n, const void* src, int64_t ls, int64_t qs, double scale,
-                                void* d_table, void* mask_ws, hipStream_t s) {
+                                void* d_table, void* mask_ws, hipStream_t s, bool overwrite) {
     if (grad_dt == H4D_F64) {
-        return eps ? tiled_g<double, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, s)
-                   : tiled_g<double, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, s);
+        return eps ? tiled_g<double, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws,
+                                           overwrite, s)
+                   : tiled_g<double, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws,
+                                            overwrite, s);
     }
-    return eps ? tiled_g<float, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, s)
-               : tiled_g<float, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, s);
+    return eps ? tiled_g<float, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, overwrite, s)
+               : tiled_g<float, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, overwrite,
+                                       s);
 }
 
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w, hipStream_t s) {

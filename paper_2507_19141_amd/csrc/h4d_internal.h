@@ -64,7 +64,7 @@ constexpr int64_t mask_stride(int64_t n) { return (n + 3) & ~(int64_t)3; }
 size_t scatter_mask_bytes(int n, int L);
 hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d_dtype grad_dt, const float* xyzt,
                                 const float* eps, int n, const void* src, int64_t lstride, int64_t qstride,
-                                double scale, void* d_table, void* mask_ws, hipStream_t s);
+                                double scale, void* d_table, void* mask_ws, hipStream_t s, bool overwrite = false);
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w,
                                  hipStream_t s);
 // Fused Adam step + optional BF16 copy + gradient zeroing (optim.hip); row in {1,2,4,8}.
@@ -116,6 +116,7 @@ struct MlpSpan {
 struct MlpBatch {
     MlpSpan s[kMaxMlpSpans];
     int count;
+    int overwrite;  // 1: d_params is written (=) instead of accumulated (+=)
 };
 
 // Persistent-grid size of the decoder kernels for a total of `queries` queries.
@@ -131,14 +132,16 @@ size_t mlp_workspace_bytes(h4d_dtype dt, int in, int out, int n);
 hipError_t launch_mlp_forward(h4d_dtype dt, int in, int out, const void* params, const void* feat, int F,
                               int64_t lstride, int64_t qstride, int n, void* delta, hipStream_t s);
 // d_out is multiplied by in_scale on load; d_feat is written times feat_scale;
-// d_params += param_scale * sum of the per-block partial gradients.
+// d_params += (or, with overwrite, =) param_scale * sum of the per-block partial gradients.
 hipError_t launch_mlp_backward(h4d_dtype dt, int in, int out, const void* params, const void* feat, int F,
                                int64_t lstride, int64_t qstride, int n, const void* d_out, double in_scale,
                                double feat_scale, double param_scale, void* d_feat, int64_t dlstride,
-                               int64_t dqstride, void* d_params, void* ws, hipStream_t s);
+                               int64_t dqstride, void* d_params, void* ws, hipStream_t s, bool overwrite = false);
 
 // ---- precision helpers (precision.hip) ----
 hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s);
+// p[0, words) = 0 (32-bit words) with a kernel, so that it may be captured in a graph.
+hipError_t launch_zero_words(void* p, int64_t words, hipStream_t s);
 hipError_t launch_count_nonfinite(const float* p, int64_t count, int32_t* counter, hipStream_t s);
 hipError_t launch_deform_apply(const float* delta, int n, int out, const float* x, const float* r, const float* s,
                                float* xo, float* ro, float* so, hipStream_t st);

@@ -755,7 +755,9 @@ __global__ __launch_bounds__(kRedParams * kRedGroups) void k_mlp_reduce(MlpBatch
         G t = G(0);
 #pragma unroll
         for (int g = 0; g < kRedGroups; ++g) t += part[g][pl];
-        static_cast<G*>(sp.d_params)[p] += scale * t;
+        G* dp = static_cast<G*>(sp.d_params) + p;
+        if (batch.overwrite) *dp = scale * t;
+        else *dp += scale * t;
     }
 }
 
@@ -927,10 +929,11 @@ hipError_t launch_mlp_forward(h4d_dtype dt, int in, int out, const void* params,
 hipError_t launch_mlp_backward(h4d_dtype dt, int in, int out, const void* params, const void* feat, int F,
                                int64_t lstride, int64_t qstride, int n, const void* d_out, double in_scale,
                                double feat_scale, double param_scale, void* d_feat, int64_t dlstride, int64_t dqstride,
-                               void* d_params, void* ws, hipStream_t s) {
+                               void* d_params, void* ws, hipStream_t s, bool overwrite) {
     if (dlstride != lstride || dqstride != qstride) return hipErrorInvalidValue;  // d_feat shares feat's layout
     const int blocks = mlp_blocks_for(dt, true, n);
-    const MlpBatch b = single(params, feat, nullptr, d_out, d_feat, d_params, F, lstride, qstride, n, blocks);
+    MlpBatch b = single(params, feat, nullptr, d_out, d_feat, d_params, F, lstride, qstride, n, blocks);
+    b.overwrite = overwrite ? 1 : 0;
     return launch_mlp_backward_batch(dt, in, out, b, blocks, in_scale, feat_scale, param_scale, ws, s);
 }
 

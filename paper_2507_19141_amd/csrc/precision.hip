@@ -20,6 +20,11 @@ __global__ __launch_bounds__(kCastBlock) void k_cast_bf16(const float* __restric
     }
 }
 
+__global__ __launch_bounds__(kCastBlock) void k_zero_words(uint32_t* __restrict__ p, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * kCastBlock + threadIdx.x; i < words; i += (int64_t)gridDim.x * kCastBlock)
+        p[i] = 0u;
+}
+
 // counter += number of NaN / Inf values in p[0, count).
 __global__ __launch_bounds__(kCastBlock) void k_count_nonfinite(const float* __restrict__ p, int64_t count,
                                                                 int32_t* __restrict__ counter) {
@@ -29,6 +34,13 @@ __global__ __launch_bounds__(kCastBlock) void k_count_nonfinite(const float* __r
     // wavefront sum, one atomic per wavefront with a non-finite value
     for (int s = 32; s > 0; s >>= 1) bad += __shfl_xor(bad, s, 64);
     if ((threadIdx.x & 63) == 0 && bad) atomicAdd(counter, bad);
+}
+
+hipError_t launch_zero_words(void* p, int64_t words, hipStream_t s) {
+    if (words <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((words + kCastBlock - 1) / kCastBlock, 4096);
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(kCastBlock), 0, s, static_cast<uint32_t*>(p), words);
+    return hipGetLastError();
 }
 
 hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s) {

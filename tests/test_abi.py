@@ -127,6 +127,12 @@ def test_entry_points_validate_without_launching():
     assert "workspace" in _lib.last_error()
     assert lib.hash4d_encode_backward(gp, 0, fake, 5, 0, fake, 1.0, fake, fake + 8, 1 << 20, None) == -1  # misaligned
     assert "aligned" in _lib.last_error()
+    OW = _lib.GRAD_OVERWRITE
+    assert lib.hash4d_encode_backward(gp, 0, fake, 5, 0x200, fake, 1.0, fake, fake, 1 << 20, None) == -1  # bad flag
+    assert "layout" in _lib.last_error()
+    assert lib.hash4d_encode_backward(gp, 0, fake, 0, OW, fake, 1.0, None, fake, 0, None) == -1  # n = 0 writes: NULL
+    assert lib.hash4d_encode(gp, 0, fake, fake, 5, OW, fake, None) == -1              # the forward has no gradient
+    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, OW, fake, 1.0, fake, None) == -1
     assert _lib.hash4d_encode_backward_workspace_bytes(g, 1000) == 1000 * 4 * 4
     # masks are level-major with the query count padded to a multiple of four
     assert _lib.hash4d_encode_backward_workspace_bytes(g, 1001) == 1004 * 4 * 4
@@ -166,3 +172,7 @@ def test_entry_points_validate_without_launching():
     assert _lib.deform_mlp_workspace_bytes(m, 0, 200_000) > 0
     assert _lib.deform_mlp_workspace_bytes(bad, 0, 200_000) == 0
     assert lib.deform_mlp_backward(mp, 0, fake, fake, 5, 0, 0, fake, 1.0, 1.0, fake, fake, fake, 8, None) == -1
+    OW = _lib.GRAD_OVERWRITE
+    assert lib.deform_mlp_backward(mp, 0, fake, fake, 0, OW, 0, fake, 1.0, 1.0, fake, None, fake, 8, None) == -1
+    assert lib.deform_mlp_backward(mp, 0, fake, fake, 0, 0, 0, fake, 1.0, 1.0, fake, None, fake, 8, None) == 0
+    assert lib.deform_mlp_forward(mp, 0, fake, fake, 5, OW, 0, fake, None) == -1            # no gradient there

@@ -113,6 +113,34 @@ def test_mlp_backward_scales_and_accumulates():
     scaled_close(d_params, init + rp, np.abs(init) + 0.5 * sp, RTOL_GRAD, "d_params +=")
 
 
+@pytest.mark.parametrize("dt", [_lib.F32, _lib.BF16, _lib.F64], ids=["f32", "bf16", "f64"])
+def test_mlp_backward_overwrite(dt):
+    # H4D_GRAD_OVERWRITE writes d_params (NaN beforehand) with exactly what accumulating
+    # into zeros gives (the per-block sums are reduced in a fixed order); n = 0 writes
+    # zeros.
+    import torch
+    n_in, n = 32, 2000
+    params, f, g = decoder_case(n_in, n, 95)
+    tdt, npdt = (torch.float64, np.float64) if dt == _lib.F64 else (torch.float32, np.float32)
+    p_dev = bf16_dev(params) if dt == _lib.BF16 else dev(params.astype(npdt))
+    f_dev, g_dev = dev(f.astype(npdt)), dev(g.astype(npdt))
+    m = _lib.mlp_shape(n_in)
+    ws_bytes = _lib.deform_mlp_workspace_bytes(m, dt, n)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    d_feat = nan_tensor((n, n_in), tdt)
+    P = O.param_count(n_in)
+    acc = torch.zeros(P, dtype=tdt, device="cuda")
+    _lib.deform_mlp_backward(m, dt, p_dev, f_dev, n, g_dev, 1.0, 0.25, d_feat, acc, ws, ws_bytes)
+    wr = nan_tensor((P,), tdt)
+    _lib.deform_mlp_backward(m, dt, p_dev, f_dev, n, g_dev, 1.0, 0.25, d_feat, wr, ws, ws_bytes,
+                             _lib.QUERY_MAJOR | _lib.GRAD_OVERWRITE)
+    assert np.array_equal(host(wr), host(acc))
+    wr.fill_(float("nan"))
+    _lib.deform_mlp_backward(m, dt, p_dev, f_dev, 0, g_dev, 1.0, 0.25, d_feat, wr, ws, ws_bytes,
+                             _lib.QUERY_MAJOR | _lib.GRAD_OVERWRITE)
+    assert (host(wr) == 0).all()
+
+
 @pytest.mark.parametrize("n_in", [8, 32])
 def test_mlp_backward_bf16_and_f64(n_in):
     params, f, g = decoder_case(n_in, 2048 + 7, 90 + n_in)

@@ -253,6 +253,34 @@ def test_encode_backward_accumulates():
     scaled_close(host(d), ref, 1.0 + O.encode_backward(x, np.abs(gf), og), RTOL_GRAD, "d_table +=")
 
 
+@pytest.mark.parametrize("dt", [_lib.F32, _lib.F64], ids=["f32", "f64"])
+def test_encode_backward_overwrite(dt):
+    # H4D_GRAD_OVERWRITE: every row of d_table is written (NaN beforehand), rows no
+    # corner reaches become zero, and n = 0 writes zeros everywhere.
+    import torch
+    og, lg, x, _, rng = encoder_case(synth.ENCODER_SMALL, 1500, 12)
+    gf = synth.upstream(x.shape[0], og.L * og.F, rng)
+    n = x.shape[0]
+    npdt, tdt = (np.float64, torch.float64) if dt == _lib.F64 else (np.float32, torch.float32)
+    d = torch.full((og.E, og.F), float("nan"), dtype=tdt, device="cuda")
+    wb = _lib.hash4d_encode_backward_workspace_bytes(lg, n)
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    for layout in (_lib.QUERY_MAJOR, _lib.LEVEL_MAJOR):
+        g_in = gf if layout == _lib.QUERY_MAJOR else gf.reshape(n, og.L, og.F).transpose(1, 0, 2)
+        d.fill_(float("nan"))
+        _lib.hash4d_encode_backward(lg, dt, dev(x), n, dev(g_in.astype(npdt)), 0.5, d, ws, wb,
+                                    layout | _lib.GRAD_OVERWRITE)
+        got = host(d)
+        assert np.isfinite(got).all()
+        ref = O.encode_backward(x, gf, og, 0.5)
+        tol = 1e-12 if dt == _lib.F64 else RTOL_GRAD
+        scaled_close(got, ref, O.encode_backward(x, np.abs(gf), og, 0.5), tol, "d_table =")
+    d.fill_(float("nan"))
+    _lib.hash4d_encode_backward(lg, dt, dev(x), 0, dev(gf.astype(npdt)), 1.0, d, ws, wb,
+                                _lib.LEVEL_MAJOR | _lib.GRAD_OVERWRITE)
+    assert (host(d) == 0).all()
+
+
 def test_encode_backward_paper_scene_full_size_property():
     # At n = 200k: <u, d_table> = <G(u), g> for random u (the backward is the exact
     # transpose of the forward), with G(u) evaluated by the oracle on every query.
