@@ -137,6 +137,24 @@ class Path:
             L_.h4d_count_nonfinite(self.d_params, self.d_params.numel(), self.counter)
         mark()
 
+    def step_smooth(self, eps, loss, sws, swb, lam: float, merged: bool):
+        """FP32 training step with the smoothness term: the step above plus Eq. 11,
+        either as the two separate calls or with the table gradient of both in one
+        scatter (hash4d_encode_backward_smooth)."""
+        L_, LM, F, OW = self.L_, self.L_.LEVEL_MAJOR, self.w.F, self.L_.GRAD_OVERWRITE
+        table, params = self.table32, self.params32
+        L_.hash4d_encode(self.g, L_.F32, table, self.xyzt, self.n, self.feat, LM)
+        L_.deform_mlp_forward(self.m, L_.F32, params, self.feat, self.n, self.delta, LM, F)
+        L_.deform_mlp_backward(self.m, L_.F32, params, self.feat, self.n, self.d_delta, 1.0, 1.0, self.d_feat,
+                               self.d_params, self.ws, self.ws_bytes, LM | OW, F)
+        if merged:
+            L_.hash4d_encode_backward_smooth(self.g, L_.F32, table, self.xyzt, eps, self.n, self.d_feat, 1.0, lam,
+                                             loss, self.d_table, sws, swb, LM | OW)
+        else:
+            L_.hash4d_encode_backward(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0, self.d_table, self.sws,
+                                      self.sws_bytes, LM | OW)
+            L_.smoothness_reg(self.g, L_.F32, table, self.xyzt, eps, self.n, lam, loss, self.d_table, sws, swb)
+
     def run(self, steps: int, warmup: int):
         t = self.torch
         for _ in range(warmup):
@@ -373,8 +391,20 @@ def smoothness_form(torch, _lib, synth, path, steps: int):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
+    # the whole FP32 training step with the term: separate calls vs one scatter
+    step_ms = {}
+    for merged in (False, True):
+        for _ in range(3):
+            path.step_smooth(eps, loss, ws, wb, 1.0, merged)
+        a.record()
+        for _ in range(steps):
+            path.step_smooth(eps, loss, ws, wb, 1.0, merged)
+        b.record()
+        torch.cuda.synchronize()
+        step_ms["one_scatter" if merged else "separate"] = a.elapsed_time(b) / steps
     return {"ms": ms, "value": n / (ms / 1e3), "unit": "queries/s", "lambda": 1.0, "sigma": 1e-3,
-            "kernels": ["k_smooth", "k_tile_mask", "k_scatter_tiled"]}
+            "kernels": ["k_smooth", "k_tile_mask", "k_scatter_tiled"],
+            "training_step_ms": step_ms, "training_step_value": n / (step_ms["one_scatter"] / 1e3)}
 
 
 def input_grad_form(torch, _lib, path, steps: int):

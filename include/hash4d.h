@@ -190,6 +190,23 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
                           const float* eps, int64_t n, float lambda, void* loss, void* d_table, void* workspace,
                           size_t ws_bytes, void* stream);
 
+/* The table gradient of a training step with the smoothness term, in one scatter:
+ * hash4d_encode_backward of d_feat (Eq. 9's transpose) plus smoothness_reg's
+ * gradient (Eq. 11), that is
+ *   *loss   += lambda / n * sum_q ||d_q||^2
+ *   d_table += grad_scale A^T d_feat + (2 lambda / n) (d w at x's corners - d w~ at x~'s)
+ * The sum is exact up to rounding order: every update of x's corners carries
+ * (2 lambda / n) d + grad_scale d_feat, every update of x~'s corners -(2 lambda / n) d.
+ * One scatter over the two corner sets replaces the plain scatter plus the pair
+ * scatter of the two separate calls.  d_feat: n L F values in `layout` (FP32; FP64
+ * for F64); layout may carry H4D_GRAD_OVERWRITE (d_table written; n = 0 writes
+ * zeros).  Other arguments as smoothness_reg; here d_table, d_feat and the
+ * workspace (smoothness_workspace_bytes) are required. */
+h4d_status hash4d_encode_backward_smooth(const h4d_grid* g, h4d_dtype table_dt, const void* table, const float* xyzt,
+                                         const float* eps, int64_t n, h4d_layout layout, const void* d_feat,
+                                         float grad_scale, float lambda, void* loss, void* d_table, void* workspace,
+                                         size_t ws_bytes, void* stream);
+
 /* ----------------------------------------------------- precision form ---- */
 
 /* dst[i] = BF16 (round to nearest even, NaN kept quiet) of the FP32 master src[i],

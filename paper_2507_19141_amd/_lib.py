@@ -102,6 +102,8 @@ SIGNATURES = {
     "hash4d_deform_apply": (_I32, [_P, _I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "smoothness_workspace_bytes": (_SZ, [_GP, _I32, _I64]),
     "smoothness_reg": (_I32, [_GP, _I32, _P, _P, _P, _I64, _F32, _P, _P, _P, _SZ, _P]),
+    "hash4d_encode_backward_smooth": (_I32, [_GP, _I32, _P, _P, _P, _I64, _I32, _P, _F32, _F32, _P, _P, _P, _SZ,
+                                             _P]),
     "h4d_cast_bf16": (_I32, [_P, _P, _I64, _P]),
     "h4d_count_nonfinite": (_I32, [_P, _I64, _P, _P]),
     "deform_mlp_workspace_bytes": (_SZ, [_MP, _I32, _I64]),
@@ -244,6 +246,15 @@ def smoothness_reg(g: Grid, table_dt: int, table, xyzt, eps, n: int, lam: float,
     _check("smoothness_reg", load().smoothness_reg(ctypes.byref(g), table_dt, ptr(table), ptr(xyzt), ptr(eps), n, lam,
                                                    ptr(loss), ptr(d_table), ptr(workspace), ws_bytes,
                                                    stream_handle(stream)))
+
+
+def hash4d_encode_backward_smooth(g: Grid, table_dt: int, table, xyzt, eps, n: int, d_feat, grad_scale: float,
+                                  lam: float, loss, d_table, workspace, ws_bytes: int, layout: int = QUERY_MAJOR,
+                                  stream=None) -> None:
+    _check("hash4d_encode_backward_smooth",
+           load().hash4d_encode_backward_smooth(ctypes.byref(g), table_dt, ptr(table), ptr(xyzt), ptr(eps), n, layout,
+                                                ptr(d_feat), grad_scale, lam, ptr(loss), ptr(d_table),
+                                                ptr(workspace), ws_bytes, stream_handle(stream)))
 
 
 # ------------------------------------------------------- precision form ----

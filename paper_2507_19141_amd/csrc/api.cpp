@@ -357,6 +357,54 @@ h4d_status smoothness_reg(const h4d_grid* g, h4d_dtype table_dt, const void* tab
                       "smoothness_reg/scatter");
 }
 
+h4d_status hash4d_encode_backward_smooth(const h4d_grid* g, h4d_dtype table_dt, const void* table, const float* xyzt,
+                                         const float* eps, int64_t n, h4d_layout layout, const void* d_feat,
+                                         float grad_scale, float lambda, void* loss, void* d_table, void* workspace,
+                                         size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    h4d_status st;
+    int64_t ls, qs;
+    const bool overwrite = (layout & H4D_GRAD_OVERWRITE) != 0;
+    layout = (h4d_layout)(layout & ~H4D_GRAD_OVERWRITE);
+    if ((st = check_grid(g)) || (st = check_dtype(table_dt)) || (st = check_xyzt(xyzt, n))) return st;
+    if ((st = feat_strides(layout, n, g->L, g->F, &ls, &qs))) return st;
+    if (!d_table) return fail(H4D_EINVAL, "d_table is NULL");
+    const hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {  // no query: nothing to add; a written gradient is zero
+        if (!overwrite) return H4D_OK;
+        const int64_t words = g->offset[g->L] * g->F * (table_dt == H4D_F64 ? 2 : 1);
+        return hip_status(launch_zero_words(d_table, words, s), "hash4d_encode_backward_smooth");
+    }
+    if (!table || !eps || !loss || !d_feat) return fail(H4D_EINVAL, "table, eps, loss or d_feat is NULL");
+    if ((st = check_table_alignment(table, table_dt, g->F))) return st;
+    if (((uintptr_t)eps) & 15u) return fail(H4D_EINVAL, "eps is not 16-byte aligned");
+    if (n * (int64_t)g->L * g->F > kMaxN) return fail(H4D_EINVAL, "n L F exceeds 2^31-1 features");
+    const size_t need = smooth_ws(g, table_dt, n);
+    if (!workspace || ws_bytes < need)
+        return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    if (((uintptr_t)workspace) & 15u) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
+    const DevGrid d = to_device(*g);
+    // pass 1: loss and d = G(x) - G(x + eps), level-major [L, n, F]
+    if ((st = hip_status(launch_smoothness(d, table_dt, table, xyzt, eps, (int)n, (double)lambda, loss, workspace, s),
+                         "hash4d_encode_backward_smooth/diff")))
+        return st;
+    // pass 2: one scatter over both corner sets: x's corners get (2 lambda / n) d +
+    // grad_scale d_feat, x~'s corners get -(2 lambda / n) d
+    int64_t rows[H4D_MAX_LEVELS];
+    rows_of(*g, rows);
+    const size_t dbytes =
+        ((size_t)n * g->L * g->F * (table_dt == H4D_F64 ? sizeof(double) : sizeof(float)) + 255) / 256 * 256;
+    MainGradArg main;
+    main.src = d_feat;
+    main.lstride = ls;
+    main.qstride = qs;
+    main.scale = (double)grad_scale;
+    return hip_status(launch_scatter_tiled(d, rows, table_dt == H4D_F64 ? H4D_F64 : H4D_F32, xyzt, eps, (int)n,
+                                           workspace, n * g->F, g->F, 2.0 * (double)lambda / (double)n, d_table,
+                                           static_cast<char*>(workspace) + dbytes, s, overwrite, main),
+                      "hash4d_encode_backward_smooth/scatter");
+}
+
 size_t hash4d_collision_workspace_bytes(const h4d_grid* g, int32_t level, int64_t n) {
     if (check_grid(g) != H4D_OK || level < 0 || level >= g->L || n < 0 || n > kMaxN) return 0;
     return census_workspace_bytes(n, g->offset[level + 1] - g->offset[level]);

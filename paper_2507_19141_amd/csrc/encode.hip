@@ -118,42 +118,65 @@ __global__ __launch_bounds__(kEncodeBlock) void k_tile_mask(DevGrid g, TileMap t
 constexpr int kScatterBlock = 1024;
 constexpr int kQueueCap = 2 * kScatterBlock;  // 128 entries per wavefront
 
+// With PAIR, a second feature gradient (the decoder's) that joins the first at x's
+// corners only: a training step with Eq. 11 then scatters both in one pass.
+template <typename G>
+struct MainGrad {
+    const G* src;  // nullptr: none
+    int64_t lstride, qstride;
+    G scale;
+};
+
 // What the scatter loads per queued query: position, gradient (and perturbation).
 template <typename G, int F, bool PAIR>
 struct TileQuery {
     float4 x;
-    float4 e;  // used when PAIR
+    float4 e;     // used when PAIR
     G gv[F];
+    G gmain[F];   // used when PAIR with a MainGrad
 };
 
 template <typename G, int F, bool PAIR>
 __device__ __forceinline__ TileQuery<G, F, PAIR> tile_load(int l, const float4* __restrict__ xyzt,
                                                            const float4* __restrict__ eps, const G* __restrict__ src,
-                                                           int64_t lstride, int64_t qstride, int q) {
+                                                           int64_t lstride, int64_t qstride, const MainGrad<G>& mg,
+                                                           int q) {
     TileQuery<G, F, PAIR> t;
     const G* gp = src + (int64_t)l * lstride + (int64_t)q * qstride;
 #pragma unroll
     for (int f = 0; f < F; ++f) t.gv[f] = gp[f];
     t.x = xyzt[q];
-    if constexpr (PAIR) t.e = eps[q];
+    if constexpr (PAIR) {
+        t.e = eps[q];
+        if (mg.src) {
+            const G* mp = mg.src + (int64_t)l * mg.lstride + (int64_t)q * mg.qstride;
+#pragma unroll
+            for (int f = 0; f < F; ++f) t.gmain[f] = mp[f];
+        }
+    }
     return t;
 }
 
 template <typename G, int F, bool PAIR>
 __device__ __forceinline__ void tile_run(const DevGrid& g, const TileMap& tm, int l, const TileQuery<G, F, PAIR>& t,
-                                         G scale, uint32_t base, uint32_t cnt, G* tile) {
+                                         G scale, const MainGrad<G>& mg, uint32_t base, uint32_t cnt, G* tile) {
     G gv[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) gv[f] = t.gv[f] * scale;
-    tile_contrib<G, F>(g, tm, l, t.x, gv, base, cnt, tile);
     if constexpr (PAIR) {
+        G gx[F], gm[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            gx[f] = mg.src ? gv[f] + t.gmain[f] * mg.scale : gv[f];
+            gm[f] = -gv[f];
+        }
+        tile_contrib<G, F>(g, tm, l, t.x, gx, base, cnt, tile);
         const float4 x = t.x, e = t.e;
         const float4 xp = make_float4(__fadd_rn(x.x, e.x), __fadd_rn(x.y, e.y), __fadd_rn(x.z, e.z),
                                       __fadd_rn(x.w, e.w));
-        G gm[F];
-#pragma unroll
-        for (int f = 0; f < F; ++f) gm[f] = -gv[f];
         tile_contrib<G, F>(g, tm, l, xp, gm, base, cnt, tile);
+    } else {
+        tile_contrib<G, F>(g, tm, l, t.x, gv, base, cnt, tile);
     }
 }
 
@@ -163,7 +186,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
                                                                 const uint32_t* __restrict__ mask,
                                                                 const G* __restrict__ src, int64_t lstride,
                                                                 int64_t qstride, G scale, G* __restrict__ d_table,
-                                                                int overwrite) {
+                                                                int overwrite, MainGrad<G> mg) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int queue[kQueueCap];
     G* tile = reinterpret_cast<G*>(smem);
@@ -178,8 +201,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
     __syncthreads();
     masked_queue_loop<kScatterBlock>(
         n, mask + (int64_t)l * mask_stride(n), bit, queue,
-        [&](int q) { return tile_load<G, F, PAIR>(l, xyzt, eps, src, lstride, qstride, q); },
-        [&](const TileQuery<G, F, PAIR>& t) { tile_run<G, F, PAIR>(g, tm, l, t, scale, base, cnt, tile); });
+        [&](int q) { return tile_load<G, F, PAIR>(l, xyzt, eps, src, lstride, qstride, mg, q); },
+        [&](const TileQuery<G, F, PAIR>& t) { tile_run<G, F, PAIR>(g, tm, l, t, scale, mg, base, cnt, tile); });
     __syncthreads();
     // the tile's rows have no other owner: add them to d_table, or with overwrite set
     // write every row (the tiles of the levels cover all E rows)
@@ -279,21 +302,22 @@ size_t scatter_mask_bytes(int n, int L) { return (size_t)mask_stride(n) * L * si
 template <typename G, int F, bool PAIR>
 static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt, const float* eps, int n,
                           const uint32_t* mask, const void* src, int64_t ls, int64_t qs, double scale, void* d_table,
-                          bool overwrite, hipStream_t s) {
+                          bool overwrite, const MainGradArg& main, hipStream_t s) {
     auto kern = k_scatter_tiled<G, F, PAIR>;
     const size_t lds = (size_t)tm.max_rows * F * sizeof(G);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(tm.tile_start[g.L]), dim3(kScatterBlock), lds, s, g, tm,
                        reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n, mask,
-                       static_cast<const G*>(src), ls, qs, (G)scale, static_cast<G*>(d_table), overwrite ? 1 : 0);
+                       static_cast<const G*>(src), ls, qs, (G)scale, static_cast<G*>(d_table), overwrite ? 1 : 0,
+                       MainGrad<G>{static_cast<const G*>(main.src), main.lstride, main.qstride, (G)main.scale});
     return hipGetLastError();
 }
 
 template <typename G, bool PAIR>
 static hipError_t tiled_g(const DevGrid& g, const int64_t* level_rows, const float* xyzt, const float* eps, int n,
                           const void* src, int64_t ls, int64_t qs, double scale, void* d_table, void* mask_ws,
-                          bool overwrite, hipStream_t s) {
+                          bool overwrite, const MainGradArg& main, hipStream_t s) {
     const TileMap tm = make_tile_map(g, level_rows, g.F, (int)sizeof(G));
     uint32_t* mask = static_cast<uint32_t*>(mask_ws);
     hipLaunchKernelGGL(k_tile_mask<PAIR>, dim3((unsigned)((n + kEncodeBlock - 1) / kEncodeBlock), (unsigned)g.L),
@@ -302,26 +326,29 @@ static hipError_t tiled_g(const DevGrid& g, const int64_t* level_rows, const flo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (g.F) {
-        case 1: return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, s);
-        case 2: return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, s);
-        case 4: return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, s);
-        case 8: return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, s);
+        case 1: return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 2: return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 4: return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 8: return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, main, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d_dtype grad_dt, const float* xyzt,
                                 const float* eps, int n, const void* src, int64_t ls, int64_t qs, double scale,
-                                void* d_table, void* mask_ws, hipStream_t s, bool overwrite) {
+                                void* d_table, void* mask_ws, hipStream_t s, bool overwrite,
+                                const MainGradArg& main) {
+    if (main.src && !eps) return hipErrorInvalidValue;  // the second gradient rides on the pair form only
     if (grad_dt == H4D_F64) {
         return eps ? tiled_g<double, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws,
-                                           overwrite, s)
+                                           overwrite, main, s)
                    : tiled_g<double, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws,
-                                            overwrite, s);
+                                            overwrite, main, s);
     }
-    return eps ? tiled_g<float, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, overwrite, s)
+    return eps ? tiled_g<float, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, overwrite,
+                                      main, s)
                : tiled_g<float, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, overwrite,
-                                       s);
+                                       main, s);
 }
 
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w, hipStream_t s) {

@@ -62,9 +62,17 @@ TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gb
 // a 16-byte boundary (the scan reads four masks per load).
 constexpr int64_t mask_stride(int64_t n) { return (n + 3) & ~(int64_t)3; }
 size_t scatter_mask_bytes(int n, int L);
+// A second feature gradient for the pair form (eps set): added, times scale, at x's
+// corners only.  src == nullptr: none.
+struct MainGradArg {
+    const void* src = nullptr;
+    int64_t lstride = 0, qstride = 0;
+    double scale = 0.0;
+};
 hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d_dtype grad_dt, const float* xyzt,
                                 const float* eps, int n, const void* src, int64_t lstride, int64_t qstride,
-                                double scale, void* d_table, void* mask_ws, hipStream_t s, bool overwrite = false);
+                                double scale, void* d_table, void* mask_ws, hipStream_t s, bool overwrite = false,
+                                const MainGradArg& main = MainGradArg{});
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w,
                                  hipStream_t s);
 // Fused Adam step + optional BF16 copy + gradient zeroing (optim.hip); row in {1,2,4,8}.

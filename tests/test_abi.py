@@ -142,6 +142,17 @@ def test_entry_points_validate_without_launching():
     assert "d_xyzt" in _lib.last_error()
     assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 0, 0, None, 1.0, None, None) == 0     # n = 0
     assert lib.hash4d_encode(None, 0, fake, fake, 5, 0, fake, None) == -1
+    sm = lib.hash4d_encode_backward_smooth
+    wbs = _lib.smoothness_workspace_bytes(g, 0, 5)
+    assert sm(gp, 0, fake, fake, fake, 5, 1, None, 1.0, 1.0, fake, fake, fake, wbs, None) == -1   # NULL d_feat
+    assert sm(gp, 0, fake, fake, fake + 4, 5, 1, fake, 1.0, 1.0, fake, fake, fake, wbs, None) == -1  # eps aligned
+    assert "eps" in _lib.last_error()
+    assert sm(gp, 0, fake, fake, fake, 5, 1, fake, 1.0, 1.0, fake, fake, fake, wbs - 4, None) == -1  # workspace
+    assert "workspace" in _lib.last_error()
+    assert sm(gp, 0, fake, fake, fake, 5, 1, fake, 1.0, 1.0, fake, None, fake, wbs, None) == -1     # NULL d_table
+    assert sm(gp, 0, fake, fake, fake, 5, 2, fake, 1.0, 1.0, fake, fake, fake, wbs, None) == -1     # unknown layout
+    assert sm(gp, 0, fake, fake, fake, 0, 1, None, 1.0, 1.0, None, fake, None, 0, None) == 0        # n = 0: no-op
+    assert sm(gp, 0, fake, fake, fake, 0, 0x101, None, 1.0, 1.0, None, None, None, 0, None) == -1   # writes: NULL
     hp = _lib.Adam(1e-3, 0.9, 0.999, 1e-8, 1, 1.0)
     hpp = _lib.ctypes.byref(hp)
     assert lib.h4d_adam_step(fake, fake, fake, fake + 4, 8, 1, hpp, None, 0, None) == -1   # misaligned v

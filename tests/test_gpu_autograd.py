@@ -94,6 +94,41 @@ def test_smoothness_bf16_table_and_f64_and_loss_only():
     assert abs(loss2 - rl32) <= RTOL_F32 * (abs(rl32) + ls)
 
 
+@pytest.mark.parametrize("dt", [_lib.F32, _lib.BF16, _lib.F64], ids=["f32", "bf16", "f64"])
+@pytest.mark.parametrize("overwrite", [False, True], ids=["accumulate", "overwrite"])
+def test_backward_with_smoothness_in_one_scatter(dt, overwrite):
+    # hash4d_encode_backward_smooth = hash4d_encode_backward(d_feat) + smoothness_reg,
+    # with one scatter over both corner sets; checked against the sum of the two
+    # oracle gradients.  Level-major d_feat; accumulate onto ones or write over NaN.
+    import torch
+    w, og, lg, x, table, _, _, eps = smooth_case(4096 + 9, 210, 3e-2)
+    n, lam, gsc = x.shape[0], 0.5, 0.25
+    gf = synth.upstream(n, og.L * og.F, np.random.default_rng(211))
+    tdt, npdt = (torch.float64, np.float64) if dt == _lib.F64 else (torch.float32, np.float32)
+    if dt == _lib.BF16:
+        bits = O.bf16_bits(table)
+        tref, tdev = O.bf16_value(bits), dev(bits.view(np.int16))
+    else:
+        tref = table.astype(npdt)
+        tdev = dev(tref)
+    loss = torch.zeros(1, dtype=tdt, device="cuda")
+    init = float("nan") if overwrite else 1.0
+    d_table = torch.full((og.E, w.F), init, dtype=tdt, device="cuda")
+    wb = _lib.smoothness_workspace_bytes(lg, dt, n)
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    g_lm = gf.reshape(n, og.L, og.F).transpose(1, 0, 2).astype(npdt)
+    layout = _lib.LEVEL_MAJOR | (_lib.GRAD_OVERWRITE if overwrite else 0)
+    _lib.hash4d_encode_backward_smooth(lg, dt, tdev, dev(x), dev(eps), n, dev(g_lm), gsc, lam, loss, d_table, ws, wb,
+                                       layout)
+    rl, rg = O.smoothness(x, eps, tref, og, lam)
+    ref = rg + O.encode_backward(x, gf, og, gsc) + (0.0 if overwrite else 1.0)
+    ls, gs = smooth_scales(og, x, eps, tref, lam)
+    scale = gs + O.encode_backward(x, np.abs(gf), og, gsc) + (0.0 if overwrite else 1.0)
+    tol_l, tol_g = (1e-10, 1e-10) if dt == _lib.F64 else (RTOL_F32, RTOL_GRAD)
+    assert abs(float(host(loss)[0]) - rl) <= tol_l * (abs(rl) + ls)
+    scaled_close(host(d_table), ref, scale, tol_g, "d_table main + smooth")
+
+
 # ------------------------------------------------------------- autograd ----
 def field(lg, n_in, dt):
     from paper_2507_19141_amd.autograd import DeformField
