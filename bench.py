@@ -127,10 +127,12 @@ class Path:
         mark()
         L_.deform_mlp_forward(self.m, self.dt, params, self.feat, self.n, self.delta, LM, F)
         mark()
+        # the decoder backward scales d_delta by S on load and writes d_feat and
+        # d_params times 1 / S, so the scatter takes d_feat unscaled (grad_scale 1)
         L_.deform_mlp_backward(self.m, self.dt, params, self.feat, self.n, self.d_delta, S, 1.0 / S, self.d_feat,
                                self.d_params, self.ws, self.ws_bytes, LM | L_.GRAD_OVERWRITE, F)
         mark()
-        L_.hash4d_encode_backward(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0 / S, self.d_table, self.sws,
+        L_.hash4d_encode_backward(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0, self.d_table, self.sws,
                                   self.sws_bytes, LM | L_.GRAD_OVERWRITE)
         if self.form == "bf16":
             L_.h4d_count_nonfinite(self.d_table, self.E * F, self.counter)
@@ -371,6 +373,20 @@ def batched_form(torch, _lib, synth, steps: int, warmup: int):
             "unbatched_ms_per_step": u_wall * 1e3 / u_steps}
 
 
+def form_differences(ref32: dict, path) -> dict:
+    """Per output of the step (features, decoder output, table and decoder
+    gradients): max and mean |BF16 form - FP32 form| on the same inputs, and the
+    max relative to the FP32 output's largest magnitude."""
+    out = {}
+    for k, a in ref32.items():
+        b = getattr(path, k)
+        d = (b.double() - a.double()).abs()
+        top = float(a.double().abs().max())
+        out[k] = {"max_abs": float(d.max()), "mean_abs": float(d.mean()), "fp32_max_abs": top,
+                  "max_rel_to_fp32_max": float(d.max()) / top if top > 0 else None}
+    return out
+
+
 def smoothness_form(torch, _lib, synth, path, steps: int):
     """Eq. 11 on the paper scene: loss and table gradient for the 200k queries and
     their perturbed copies (sigma = 1e-3), FP32 table, timed on its own."""
@@ -586,6 +602,8 @@ def main():
     fp32 = Path(torch, _lib, synth, "fp32")
     wall, gpu_ms, per = fp32.run(args.steps, args.warmup)
     n = fp32.n
+    # the FP32 step's outputs, kept to report the BF16 form against them
+    ref32 = {k: getattr(fp32, k).clone() for k in ("feat", "delta", "d_table", "d_params")}
     ms_per_step = wall * 1e3 / args.steps
     value = n * args.steps / wall
     ab = algorithmic_bytes(fp32.w.L, fp32.w.F, 4)
@@ -617,9 +635,10 @@ def main():
     bf = Path(torch, _lib, synth, "bf16")
     wall_b, gpu_b, per_b = bf.run(args.steps, args.warmup)
     result["forms"] = {"bf16": {"value": n * args.steps / wall_b, "ms_per_step": wall_b * 1e3 / args.steps,
-                                "kernels_ms": per_b, "loss_scale": bf.loss_scale},
+                                "kernels_ms": per_b, "loss_scale": bf.loss_scale,
+                                "vs_fp32": form_differences(ref32, bf)},
                        "smoothness": smooth}
-    del bf
+    del bf, ref32
     torch.cuda.empty_cache()
     if not args.no_batched:
         result["forms"]["batched"] = batched_form(torch, _lib, synth, max(3, args.steps // 5), 2)
