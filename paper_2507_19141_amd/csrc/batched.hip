@@ -55,11 +55,19 @@ __device__ __forceinline__ int find_range(const BRange* __restrict__ r, int nr, 
     return lo;
 }
 
-template <typename TT, int F>
+// Workgroups go to the eight XCDs round-robin by id, so with a grid of whole rounds
+// XCD x walks its own contiguous eighth of the item list: at any time each XCD's L2
+// holds the level slices of its own part of the list instead of every XCD streaming
+// the same slice.  PAIRS: row-pair corner loads (gather_corners).
+template <typename TT, int F, bool PAIRS>
 __global__ __launch_bounds__(kBatchBlock) void k_bencode(const BSeg* __restrict__ segs, const DevGrid* __restrict__ grids,
                                                          const BRange* __restrict__ ranges, int nranges, int total,
                                                          BSchedule sch) {
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int nx = (gridDim.x % kXcds) == 0 ? kXcds : 1;
+    const int x = (int)blockIdx.x % nx, slots = (int)gridDim.x / nx;
+    const int per = (total + nx - 1) / nx;
+    const int end = min(total, (x + 1) * per);
+    for (int item = x * per + (int)blockIdx.x / nx; item < end; item += slots) {
         const BRange rg = ranges[find_range(ranges, nranges, item)];
         const BSeg sg = segs[rg.seg];
         const DevGrid& g = grids[sg.scene];
@@ -76,8 +84,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_bencode(const BSeg* __restrict_
                 uint32_t row[16];
                 level_rows(g, l, c, row);
                 float v[16][F];
-#pragma unroll
-                for (int k = 0; k < 16; ++k) RowLoad<TT, F, float>::load(table, row[k], v[k]);
+                gather_corners<TT, F, PAIRS>(g, table, row, v);
                 float w[16];
                 level_weights<float>(c, w);
                 float acc[F];
@@ -250,21 +257,31 @@ static hipError_t launch_bencode(const h4d_batched_plan& p, const BSchedule& s, 
     if (p.total_enc == 0) return hipSuccess;
     const int F = p.scenes[0].grid.F;
     const dim3 grid(std::min(s.grid, p.total_enc)), block(kBatchBlock);
-#define H4D_BENC(TT, FF) hipLaunchKernelGGL((k_bencode<TT, FF>), grid, block, 0, st, p.segs, p.grids, p.ranges_enc, \
-                                            p.nranges_enc, p.total_enc, s)
+    // row-pair loads need every scene's table aligned to two rows
+    const size_t pair_bytes = 2 * 2 * (p.dt == H4D_BF16 ? sizeof(uint16_t) : sizeof(float));
+    bool pairs = F == 2;
+    for (const h4d_scene_desc& d : p.scenes) pairs = pairs && ((uintptr_t)d.table % pair_bytes) == 0;
+#define H4D_BENC(TT, FF, PP) hipLaunchKernelGGL((k_bencode<TT, FF, PP>), grid, block, 0, st, p.segs, p.grids, \
+                                                p.ranges_enc, p.nranges_enc, p.total_enc, s)
     if (p.dt == H4D_BF16) {
         switch (F) {
-            case 1: H4D_BENC(bf16_t, 1); break;
-            case 2: H4D_BENC(bf16_t, 2); break;
-            case 4: H4D_BENC(bf16_t, 4); break;
-            default: H4D_BENC(bf16_t, 8); break;
+            case 1: H4D_BENC(bf16_t, 1, false); break;
+            case 2:
+                if (pairs) H4D_BENC(bf16_t, 2, true);
+                else H4D_BENC(bf16_t, 2, false);
+                break;
+            case 4: H4D_BENC(bf16_t, 4, false); break;
+            default: H4D_BENC(bf16_t, 8, false); break;
         }
     } else {
         switch (F) {
-            case 1: H4D_BENC(float, 1); break;
-            case 2: H4D_BENC(float, 2); break;
-            case 4: H4D_BENC(float, 4); break;
-            default: H4D_BENC(float, 8); break;
+            case 1: H4D_BENC(float, 1, false); break;
+            case 2:
+                if (pairs) H4D_BENC(float, 2, true);
+                else H4D_BENC(float, 2, false);
+                break;
+            case 4: H4D_BENC(float, 4, false); break;
+            default: H4D_BENC(float, 8, false); break;
         }
     }
 #undef H4D_BENC

@@ -12,11 +12,8 @@ namespace h4d {
 
 constexpr int kEncodeBlock = 256;
 
-// PAIRS (F = 2 FP32 / BF16 tables aligned to two rows): the two corners of an x-pair
-// (same y, z, t) sit in rows r0 and r0 ^ 1 whenever their hashes differ only in bit
-// 0 (pi_1 = 1 and an even lower x index; r1 = r0 + 1 on dense levels with r0 even),
-// and one aligned load of the row pair then serves both corners.  The loads change;
-// the arithmetic (and its order) does not.
+// PAIRS: row-pair loads (gather_corners).  The loads change; the arithmetic (and its
+// order) does not.
 template <typename TT, int F, bool PAIRS>
 __global__ __launch_bounds__(kEncodeBlock) void k_encode(DevGrid g, const TT* __restrict__ table,
                                                          const float4* __restrict__ xyzt, int n,
@@ -32,32 +29,7 @@ __global__ __launch_bounds__(kEncodeBlock) void k_encode(DevGrid g, const TT* __
     uint32_t row[16];
     level_rows(g, l, c, row);
     A v[16][F];
-    if constexpr (PAIRS) {
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const uint32_t r0 = row[2 * p], r1 = row[2 * p + 1];
-            const uint32_t a = r0 & ~1u;
-            if (a + 1u < g.rows) {
-                A lo[2], hi[2];
-                RowPairLoad<TT, A>::load(table, a, lo, hi);
-                const bool odd = r0 & 1u;
-#pragma unroll
-                for (int f = 0; f < 2; ++f) v[2 * p][f] = odd ? hi[f] : lo[f];
-                if (r1 == (r0 ^ 1u)) {
-#pragma unroll
-                    for (int f = 0; f < 2; ++f) v[2 * p + 1][f] = odd ? lo[f] : hi[f];
-                } else {
-                    RowLoad<TT, F, A>::load(table, r1, v[2 * p + 1]);
-                }
-            } else {
-                RowLoad<TT, F, A>::load(table, r0, v[2 * p]);
-                RowLoad<TT, F, A>::load(table, r1, v[2 * p + 1]);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) RowLoad<TT, F, A>::load(table, row[k], v[k]);
-    }
+    gather_corners<TT, F, PAIRS>(g, table, row, v);
     A w[16];
     level_weights<A>(c, w);
     A acc[F];

@@ -14,38 +14,6 @@ namespace h4d {
 
 constexpr int kSmoothBlock = 256;
 
-// The 16 corner rows of one cell into v; PAIRS as in the encoder's forward.
-template <typename TT, int F, bool PAIRS, typename A>
-__device__ __forceinline__ void gather_corners(const DevGrid& g, const TT* __restrict__ table,
-                                               const uint32_t (&row)[16], A (&v)[16][F]) {
-    if constexpr (PAIRS) {
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const uint32_t r0 = row[2 * p], r1 = row[2 * p + 1];
-            const uint32_t a = r0 & ~1u;
-            if (a + 1u < g.rows) {
-                A lo[2], hi[2];
-                RowPairLoad<TT, A>::load(table, a, lo, hi);
-                const bool odd = r0 & 1u;
-#pragma unroll
-                for (int f = 0; f < 2; ++f) v[2 * p][f] = odd ? hi[f] : lo[f];
-                if (r1 == (r0 ^ 1u)) {
-#pragma unroll
-                    for (int f = 0; f < 2; ++f) v[2 * p + 1][f] = odd ? lo[f] : hi[f];
-                } else {
-                    RowLoad<TT, F, A>::load(table, r1, v[2 * p + 1]);
-                }
-            } else {
-                RowLoad<TT, F, A>::load(table, r0, v[2 * p]);
-                RowLoad<TT, F, A>::load(table, r1, v[2 * p + 1]);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) RowLoad<TT, F, A>::load(table, row[k], v[k]);
-    }
-}
-
 template <typename TT, int F, bool PAIRS>
 __global__ __launch_bounds__(kSmoothBlock) void k_smooth(DevGrid g, const TT* __restrict__ table,
                                                          const float4* __restrict__ xyzt,
