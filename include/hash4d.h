@@ -154,10 +154,17 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
  * clamp is active (x_d < 0, x_d > 1 or NaN), the inner one-sided derivative at 0
  * and 1.  table_dt F32 / BF16: d_feat and d_xyzt FP32; F64: both FP64.
  *   table [E, F]   d_feat n L F values in `layout`   d_xyzt [n, 4] (+=)
- * One thread per query walks the levels; every (q, d) output has one writer. */
+ * workspace NULL (or table_dt F64): one thread per query walks the levels.
+ * Otherwise `workspace` (device, 16-byte aligned, at least
+ * hash4d_encode_backward_input_workspace_bytes, i.e. L n 16 bytes) holds each
+ * level's four terms: one pass per (query, level), placed on the XCDs level by
+ * level, then a pass that sums the levels in order.  Either way every (q, d) output
+ * has one writer. */
+size_t hash4d_encode_backward_input_workspace_bytes(const h4d_grid* g, h4d_dtype table_dt, int64_t n);
 h4d_status hash4d_encode_backward_input(const h4d_grid* g, h4d_dtype table_dt, const void* table,
                                         const float* xyzt, int64_t n, h4d_layout layout, const void* d_feat,
-                                        float grad_scale, void* d_xyzt, void* stream);
+                                        float grad_scale, void* d_xyzt, void* workspace, size_t ws_bytes,
+                                        void* stream);
 
 /* Test hook: the table row (level offset included) and FP32 weight of the 16
  * corners of every query and level.  Corner c is upper along x, y, z, t iff bit

@@ -97,7 +97,8 @@ SIGNATURES = {
     "hash4d_encode": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _P]),
     "hash4d_encode_backward_workspace_bytes": (_SZ, [_GP, _I64]),
     "hash4d_encode_backward": (_I32, [_GP, _I32, _P, _I64, _I32, _P, _F32, _P, _P, _SZ, _P]),
-    "hash4d_encode_backward_input": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _F32, _P, _P]),
+    "hash4d_encode_backward_input_workspace_bytes": (_SZ, [_GP, _I32, _I64]),
+    "hash4d_encode_backward_input": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _F32, _P, _P, _SZ, _P]),
     "hash4d_corner_indices": (_I32, [_GP, _P, _I64, _P, _P, _P]),
     "hash4d_deform_apply": (_I32, [_P, _I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "smoothness_workspace_bytes": (_SZ, [_GP, _I32, _I64]),
@@ -218,11 +219,16 @@ def hash4d_encode_backward(g: Grid, grad_dt: int, xyzt, n: int, d_feat, grad_sca
                                          ptr(d_table), ptr(workspace), ws_bytes, stream_handle(stream)))
 
 
+def hash4d_encode_backward_input_workspace_bytes(g: Grid, table_dt: int, n: int) -> int:
+    return load().hash4d_encode_backward_input_workspace_bytes(ctypes.byref(g), table_dt, n)
+
+
 def hash4d_encode_backward_input(g: Grid, table_dt: int, table, xyzt, n: int, d_feat, grad_scale: float, d_xyzt,
-                                 layout: int = QUERY_MAJOR, stream=None) -> None:
+                                 layout: int = QUERY_MAJOR, workspace=None, ws_bytes: int = 0, stream=None) -> None:
     _check("hash4d_encode_backward_input",
            load().hash4d_encode_backward_input(ctypes.byref(g), table_dt, ptr(table), ptr(xyzt), n, layout,
-                                               ptr(d_feat), grad_scale, ptr(d_xyzt), stream_handle(stream)))
+                                               ptr(d_feat), grad_scale, ptr(d_xyzt), ptr(workspace), ws_bytes,
+                                               stream_handle(stream)))
 
 
 def hash4d_corner_indices(g: Grid, xyzt, n: int, rows, w, stream=None) -> None:

@@ -280,9 +280,16 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
                       "hash4d_encode_backward");
 }
 
+size_t hash4d_encode_backward_input_workspace_bytes(const h4d_grid* g, h4d_dtype table_dt, int64_t n) {
+    if (check_grid(g) != H4D_OK || check_dtype(table_dt) != H4D_OK || n < 0 || n > kMaxN) return 0;
+    if (table_dt == H4D_F64) return 0;  // the FP64 form runs in one pass
+    return input_grad_workspace_bytes(g->L, (int)n);
+}
+
 h4d_status hash4d_encode_backward_input(const h4d_grid* g, h4d_dtype table_dt, const void* table,
                                         const float* xyzt, int64_t n, h4d_layout layout, const void* d_feat,
-                                        float grad_scale, void* d_xyzt, void* stream) {
+                                        float grad_scale, void* d_xyzt, void* workspace, size_t ws_bytes,
+                                        void* stream) {
     g_last_error.clear();
     h4d_status st;
     int64_t ls, qs;
@@ -293,9 +300,17 @@ h4d_status hash4d_encode_backward_input(const h4d_grid* g, h4d_dtype table_dt, c
     if ((st = check_table_alignment(table, table_dt, g->F))) return st;
     if (((uintptr_t)d_xyzt) & (table_dt == H4D_F64 ? 31u : 15u))
         return fail(H4D_EINVAL, "d_xyzt is not aligned to its row (%d bytes)", table_dt == H4D_F64 ? 32 : 16);
+    void* ws = nullptr;
+    if (workspace && table_dt != H4D_F64) {
+        const size_t need = input_grad_workspace_bytes(g->L, (int)n);
+        if (ws_bytes < need) return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+        if (((uintptr_t)workspace) & 15u) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
+        if (n * (int64_t)g->L > kMaxN) return fail(H4D_EINVAL, "n L exceeds 2^31-1 level terms");
+        ws = workspace;
+    }
     const DevGrid d = to_device(*g);
     return hip_status(launch_encode_input_grad(d, table_dt, table, xyzt, (int)n, d_feat, ls, qs, (double)grad_scale,
-                                               d_xyzt, (hipStream_t)stream),
+                                               d_xyzt, (hipStream_t)stream, ws),
                       "hash4d_encode_backward_input");
 }
 

@@ -88,9 +88,12 @@ size_t decompose_workspace_bytes(int64_t n);
 hipError_t launch_decompose(const float* dp, int64_t n, double k_percent, float lam_s, int32_t* dyn_idx,
                             int32_t* n_dynamic, uint8_t* is_dyn, float* loss, float* d_dp, void* ws, hipStream_t s);
 // d_xyzt[q] += scale * d<f_h, d_feat>/dx (encode_input.hip).
+// ws (FP32 / BF16 tables; at least input_grad_workspace_bytes, 16-byte aligned):
+// the two-pass, level-placed form; nullptr (or FP64): one pass, one thread per query.
 hipError_t launch_encode_input_grad(const DevGrid& g, h4d_dtype dt, const void* table, const float* xyzt, int n,
                                     const void* d_feat, int64_t lstride, int64_t qstride, double scale, void* d_xyzt,
-                                    hipStream_t s);
+                                    hipStream_t s, void* ws = nullptr);
+size_t input_grad_workspace_bytes(int L, int n);
 
 // ---- decoder launchers (mlp.hip) ----
 constexpr int kMaxMlpSpans = 16;

@@ -132,15 +132,21 @@ def test_entry_points_validate_without_launching():
     assert "layout" in _lib.last_error()
     assert lib.hash4d_encode_backward(gp, 0, fake, 0, OW, fake, 1.0, None, fake, 0, None) == -1  # n = 0 writes: NULL
     assert lib.hash4d_encode(gp, 0, fake, fake, 5, OW, fake, None) == -1              # the forward has no gradient
-    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, OW, fake, 1.0, fake, None) == -1
+    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, OW, fake, 1.0, fake, None, 0, None) == -1
     assert _lib.hash4d_encode_backward_workspace_bytes(g, 1000) == 1000 * 4 * 4
     # masks are level-major with the query count padded to a multiple of four
     assert _lib.hash4d_encode_backward_workspace_bytes(g, 1001) == 1004 * 4 * 4
     assert lib.hash4d_corner_indices(gp, fake, 5, None, None, None) == -1
-    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, 0, fake, 1.0, None, None) == -1   # NULL d_xyzt
-    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, 0, fake, 1.0, fake + 8, None) == -1
+    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, 0, fake, 1.0, None, None, 0, None) == -1  # NULL d_xyzt
+    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, 0, fake, 1.0, fake + 8, None, 0, None) == -1
     assert "d_xyzt" in _lib.last_error()
-    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 0, 0, None, 1.0, None, None) == 0     # n = 0
+    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 0, 0, None, 1.0, None, None, 0, None) == 0  # n = 0
+    wbi = _lib.hash4d_encode_backward_input_workspace_bytes(g, 0, 5)
+    assert wbi == 5 * g.L * 16 and _lib.hash4d_encode_backward_input_workspace_bytes(g, 2, 5) == 0
+    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, 0, fake, 1.0, fake, fake, wbi - 1, None) == -1
+    assert "workspace" in _lib.last_error()
+    assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, 0, fake, 1.0, fake, fake + 8, wbi, None) == -1
+    assert "aligned" in _lib.last_error()
     assert lib.hash4d_encode(None, 0, fake, fake, 5, 0, fake, None) == -1
     sm = lib.hash4d_encode_backward_smooth
     wbs = _lib.smoothness_workspace_bytes(g, 0, 5)

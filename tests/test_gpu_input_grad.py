@@ -33,7 +33,7 @@ def magnitude(x, table, g, gf):
     return out
 
 
-def run(lg, dt, table_dev, x, gf, scale=1.0, layout=_lib.QUERY_MAJOR, start=None):
+def run(lg, dt, table_dev, x, gf, scale=1.0, layout=_lib.QUERY_MAJOR, start=None, two_pass=False):
     import torch
     n = x.shape[0]
     fdt = torch.float64 if dt == _lib.F64 else torch.float32
@@ -41,17 +41,23 @@ def run(lg, dt, table_dev, x, gf, scale=1.0, layout=_lib.QUERY_MAJOR, start=None
     g = np.asarray(gf, np.float64 if dt == _lib.F64 else np.float32)
     if layout == _lib.LEVEL_MAJOR:
         g = np.ascontiguousarray(g.reshape(n, lg.L, lg.F).transpose(1, 0, 2))
-    _lib.hash4d_encode_backward_input(lg, dt, table_dev, dev(x), n, dev(g), scale, out, layout)
+    ws, wb = None, 0
+    if two_pass:   # the level-placed form: per-level terms in a workspace, then a sum
+        wb = _lib.hash4d_encode_backward_input_workspace_bytes(lg, dt, n)
+        assert wb == n * lg.L * 16
+        ws = torch.full((wb // 4,), float("nan"), device="cuda")
+    _lib.hash4d_encode_backward_input(lg, dt, table_dev, dev(x), n, dev(g), scale, out, layout, ws, wb)
     return host(out)
 
 
-@pytest.mark.parametrize("dt", [_lib.F32, _lib.F64], ids=["f32", "f64"])
+@pytest.mark.parametrize("dt,two_pass", [(_lib.F32, False), (_lib.F32, True), (_lib.F64, False)],
+                         ids=["f32", "f32-two-pass", "f64"])
 @pytest.mark.parametrize("layout", [_lib.QUERY_MAJOR, _lib.LEVEL_MAJOR], ids=["query-major", "level-major"])
-def test_input_grad_small(dt, layout):
+def test_input_grad_small(dt, two_pass, layout):
     og, lg, x, table, rng = encoder_case(synth.ENCODER_SMALL, 4096, 30, table_scale=1.0)
     gf = synth.upstream(x.shape[0], og.L * og.F, rng)
     t = table.astype(np.float64) if dt == _lib.F64 else table
-    got = run(lg, dt, dev(t), x, gf, 0.5, layout)
+    got = run(lg, dt, dev(t), x, gf, 0.5, layout, two_pass=two_pass)
     ref = O.encode_backward_input(x, t, og, gf, 0.5)
     scaled_close(got, ref, 0.5 * magnitude(x, t, og, gf), 1e-12 if dt == _lib.F64 else RTOL_F32, "d_xyzt")
     # out-of-range and NaN coordinates carry no gradient
@@ -59,17 +65,19 @@ def test_input_grad_small(dt, layout):
     assert np.all(got[bad] == 0)
 
 
-def test_input_grad_bf16_table_exact_inputs():
+@pytest.mark.parametrize("two_pass", [False, True], ids=["one-pass", "two-pass"])
+def test_input_grad_bf16_table_exact_inputs(two_pass):
     og, lg, x, table, rng = encoder_case(synth.ENCODER_SMALL, 4096, 31, table_scale=1.0)
     gf = synth.upstream(x.shape[0], og.L * og.F, rng)
     bits = O.bf16_bits(table)
     tb = O.bf16_value(bits)
-    got = run(lg, _lib.BF16, dev(bits.view(np.int16)), x, gf)
+    got = run(lg, _lib.BF16, dev(bits.view(np.int16)), x, gf, two_pass=two_pass)
     scaled_close(got, O.encode_backward_input(x, tb, og, gf), magnitude(x, tb, og, gf), RTOL_F32, "d_xyzt bf16")
 
 
+@pytest.mark.parametrize("two_pass", [False, True], ids=["one-pass", "two-pass"])
 @pytest.mark.parametrize("F,T,n,L", [(1, 3000, 1037, 3), (4, 1 << 12, 777, 4), (8, 1 << 10, 300, 2)])
-def test_input_grad_widths_and_ragged(F, T, n, L):
+def test_input_grad_widths_and_ragged(F, T, n, L, two_pass):
     rs = O.doubling_resolutions(3, 40, L)
     rt = O.doubling_resolutions(2, 9, L)
     og = O.make_grid(L, F, rs, rt, T)
@@ -79,29 +87,31 @@ def test_input_grad_widths_and_ragged(F, T, n, L):
     x = np.concatenate([x, edge_points(og)])
     table = synth.table_init(og.E, F, rng, 1.0)
     gf = synth.upstream(x.shape[0], L * F, rng)
-    got = run(lg, _lib.F32, dev(table), x, gf)
+    got = run(lg, _lib.F32, dev(table), x, gf, two_pass=two_pass)
     scaled_close(got, O.encode_backward_input(x, table, og, gf), magnitude(x, table, og, gf), RTOL_F32, "d_xyzt")
 
 
-def test_input_grad_paper_scene_full_size_sampled():
+@pytest.mark.parametrize("two_pass", [False, True], ids=["one-pass", "two-pass"])
+def test_input_grad_paper_scene_full_size_sampled(two_pass):
     # the whole 200k-query scene runs; 4096 sampled queries are checked (each output
     # row depends on its own query only)
     w = synth.PAPER_SCENE
     og, lg, x, table, rng = encoder_case(w, w.n, 33, edges=False, table_scale=1.0)
     gf = synth.upstream(w.n, og.L * og.F, rng)
-    got = run(lg, _lib.F32, dev(table), x, gf, layout=_lib.LEVEL_MAJOR)
+    got = run(lg, _lib.F32, dev(table), x, gf, layout=_lib.LEVEL_MAJOR, two_pass=two_pass)
     idx = np.random.default_rng(34).choice(w.n, 4096, replace=False)
     xs, gs = x[idx], gf[idx]
     scaled_close(got[idx], O.encode_backward_input(xs, table, og, gs), magnitude(xs, table, og, gs), RTOL_F32,
                  "d_xyzt 200k")
 
 
-def test_input_grad_accumulates_and_n0_is_noop():
+@pytest.mark.parametrize("two_pass", [False, True], ids=["one-pass", "two-pass"])
+def test_input_grad_accumulates_and_n0_is_noop(two_pass):
     import torch
     og, lg, x, table, rng = encoder_case(synth.ENCODER_SMALL, 1000, 35, edges=False, table_scale=1.0)
     gf = synth.upstream(x.shape[0], og.L * og.F, rng)
     start = torch.full((x.shape[0], 4), 2.0, device="cuda")
-    got = run(lg, _lib.F32, dev(table), x, gf, start=start)
+    got = run(lg, _lib.F32, dev(table), x, gf, start=start, two_pass=two_pass)
     ref = 2.0 + O.encode_backward_input(x, table, og, gf)
     scaled_close(got, ref, 2.0 + magnitude(x, table, og, gf), RTOL_F32, "d_xyzt +=")
     out = torch.full((4, 4), 7.0, device="cuda")
