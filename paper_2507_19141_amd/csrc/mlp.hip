@@ -353,8 +353,13 @@ __device__ __forceinline__ void load_biases(const typename Pol::S* __restrict__ 
 }
 
 // ---------------------------------------------------------------- forward ----
+// Four wavefronts per SIMD (128 VGPRs) where the layer chain fits without spilling.
 template <class Pol, int IN>
-__global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(MlpBatch batch, int out) {
+constexpr int fwd_waves_per_eu() { return (std::is_same<Pol, PolF64>::value || IN > 32) ? 1 : 4; }
+
+template <class Pol, int IN>
+__global__ __launch_bounds__(kMlpBlock) __attribute__((amdgpu_waves_per_eu(fwd_waves_per_eu<Pol, IN>())))
+void k_mlp_forward(MlpBatch batch, int out) {
     using Sh = Shape<Pol, IN>;
     using V = typename Pol::V;
     constexpr bool kLds = !std::is_same<Pol, PolF64>::value;
