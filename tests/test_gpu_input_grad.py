@@ -117,3 +117,42 @@ def test_input_grad_accumulates_and_n0_is_noop(two_pass):
     out = torch.full((4, 4), 7.0, device="cuda")
     _lib.hash4d_encode_backward_input(lg, _lib.F32, dev(table), dev(x[:4]), 0, dev(gf[:4]), 1.0, out)
     assert (host(out) == 7.0).all()
+
+
+@pytest.mark.parametrize("two_pass", [False, True], ids=["one-pass", "two-pass"])
+def test_position_gradient_through_the_decoder(two_pass):
+    # dDelta/dP composed from the entry points: d_delta -> deform_mlp_backward ->
+    # d_feat -> hash4d_encode_backward_input -> d_xyzt, against the same chain of
+    # oracle functions (decoder backward on the oracle's features, then the input
+    # gradient of the encoder).
+    import torch
+    from tests.util import RTOL_GRAD, mlp_backward_scale
+    from tests.util import lib_grid, oracle_grid
+    w = synth.SMALL_DECODER
+    og, lg = oracle_grid(w), lib_grid(w)
+    assert_same_layout(og, lg)
+    rng, x = synth.small_inputs(41, 3000)
+    n = x.shape[0]
+    table = synth.table_init(og.E, w.F, rng)
+    params = synth.decoder_params(w.n_in, rng)
+    gd = synth.upstream(n, 10, rng)
+    LM = _lib.LEVEL_MAJOR
+    m = _lib.mlp_shape(w.n_in)
+    td, xd = dev(table), dev(x)
+    feat = torch.empty((w.L, n, w.F), device="cuda")
+    _lib.hash4d_encode(lg, _lib.F32, td, xd, n, feat, LM)
+    wb = _lib.deform_mlp_workspace_bytes(m, _lib.F32, n)
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    d_feat = torch.empty((w.L, n, w.F), device="cuda")
+    d_params = torch.empty(O.param_count(w.n_in), device="cuda")
+    _lib.deform_mlp_backward(m, _lib.F32, dev(params), feat, n, dev(gd), 1.0, 1.0, d_feat, d_params, ws, wb,
+                             LM | _lib.GRAD_OVERWRITE, w.F)
+    d_xyzt = torch.zeros((n, 4), device="cuda")
+    wi = _lib.hash4d_encode_backward_input_workspace_bytes(lg, _lib.F32, n) if two_pass else 0
+    wsi = torch.empty(max(wi, 1), dtype=torch.uint8, device="cuda") if two_pass else None
+    _lib.hash4d_encode_backward_input(lg, _lib.F32, td, xd, n, d_feat, 1.0, d_xyzt, LM, wsi, wi)
+    f_ref = O.encode(x, table, og)
+    rf, _ = O.mlp_backward(params, f_ref, gd)
+    ref = O.encode_backward_input(x, table, og, rf)
+    sf, _ = mlp_backward_scale(params, f_ref, gd)
+    scaled_close(host(d_xyzt), ref, magnitude(x, table, og, sf), RTOL_GRAD, "dDelta/dP")
