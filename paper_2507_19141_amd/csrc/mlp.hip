@@ -74,11 +74,13 @@ struct PolBF16 {
     static constexpr int KC = 32, E = 8;
     __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
     __device__ static float get(const Acc& a, int r) { return a[r]; }
+    // activations to BF16 operands with gfx950's packed conversion (round to nearest
+    // even, as f32_to_bf16 does for every finite value)
     __device__ static Op pack(const V* v) {
-        ushortx8 u;
+        bf16x8 r;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) u[e] = f32_to_bf16(v[e]);
-        return __builtin_bit_cast(bf16x8, u);
+        for (int e = 0; e < 8; ++e) r[e] = (__bf16)v[e];
+        return r;
     }
     __device__ static Op frag(const FE* p) {
         return __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushortx8*>(p));
@@ -443,8 +445,8 @@ __device__ __forceinline__ void wmma(typename Pol::Acc& acc, const WOp<Pol>& a, 
         shortx4 x, y;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            x[e] = (short)f32_to_bf16(a.v[e]);
-            y[e] = (short)f32_to_bf16(b.v[e]);
+            x[e] = __builtin_bit_cast(short, (__bf16)a.v[e]);
+            y[e] = __builtin_bit_cast(short, (__bf16)b.v[e]);
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, acc, 0, 0, 0);
     } else {
