@@ -24,7 +24,7 @@ rounding decides an integer: the scaling x * N_l is done in FP32 (round to
 nearest even, no fused multiply-add), so that floor() and therefore the corner
 indices are bit-identical to the kernel's.
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
 
  R1  Eq. 7 prints no level exponent; read as N_l = floor(N_min * b**l), the
      progression of the hash encoding it builds on.  FP64 evaluation is snapped
