@@ -392,7 +392,7 @@ void k_mlp_forward(MlpBatch batch, int out) {
     load_tile(tile, next);
     for (; tile < ntiles; tile += stride) {
         // Weight fragments are read from LDS at each use rather than held in registers
-        // across the loop: the smaller register footprint fits three wavefronts per SIMD.
+        // across the loop: the smaller register footprint fits four wavefronts per SIMD.
         asm volatile("" ::: "memory");
         const int seg = tile / tps;
         const int q = (tile - seg * tps) * 16 + j;
