@@ -11,7 +11,8 @@
  *    enqueued asynchronously on it; arguments are validated synchronously first.
  *  - Every call returns an h4d_status.  On a negative status nothing has been
  *    enqueued and h4d_last_error() (thread-local, static storage) says why.
- *  - n == 0 is valid and enqueues nothing.  n must not exceed 2^31 - 1.
+ *  - n == 0 is valid and enqueues nothing.  n must not exceed 2^31 - 2^16 (query
+ *    counts padded to whole workgroups stay inside 32-bit kernel arithmetic).
  *  - Gradient outputs ACCUMULATE (+=) unless stated otherwise, so the caller
  *    zeroes them first.
  *  - Tables [E, F] are aligned to their row size, at most 16 bytes (H4D_EINVAL

@@ -31,7 +31,10 @@ static h4d_status hip_status(hipError_t e, const char* where) {
 static const uint32_t kPrimes[4] = {1u, 2654435761u, 805459861u, 3266489917u};
 static const int64_t kMaxRes = (int64_t)1 << 24;
 static const int64_t kMaxT = (int64_t)1 << 30;
-static const int64_t kMaxN = 2147483647;
+static const int64_t kMaxN = 2147483647;  // element counts (features, outputs) per call
+// Queries per call: 2^31 - 2^16, so that query counts padded to whole workgroups or
+// MFMA tiles (n + 255, n + 15, ...) stay inside the kernels' 32-bit arithmetic.
+static const int64_t kMaxQ = kMaxN - 65535;
 
 static bool valid_F(int F) { return F == 1 || F == 2 || F == 4 || F == 8; }
 
@@ -92,7 +95,7 @@ DevGrid to_device(const h4d_grid& g) {
 }
 
 static h4d_status check_xyzt(const float* xyzt, int64_t n) {
-    if (n < 0 || n > kMaxN) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-1", (long long)n);
+    if (n < 0 || n > kMaxQ) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-2^16", (long long)n);
     if (n > 0 && !xyzt) return fail(H4D_EINVAL, "xyzt is NULL");
     if (((uintptr_t)xyzt) & 15u) return fail(H4D_EINVAL, "xyzt is not 16-byte aligned");
     return H4D_OK;
@@ -246,7 +249,7 @@ h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* tabl
 }
 
 size_t hash4d_encode_backward_workspace_bytes(const h4d_grid* g, int64_t n) {
-    if (check_grid(g) != H4D_OK || n < 0 || n > kMaxN || n * (int64_t)g->L > kMaxN) return 0;
+    if (check_grid(g) != H4D_OK || n < 0 || n > kMaxQ || n * (int64_t)g->L > kMaxN) return 0;
     return scatter_mask_bytes((int)n, g->L);
 }
 
@@ -281,7 +284,7 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
 }
 
 size_t hash4d_encode_backward_input_workspace_bytes(const h4d_grid* g, h4d_dtype table_dt, int64_t n) {
-    if (check_grid(g) != H4D_OK || check_dtype(table_dt) != H4D_OK || n < 0 || n > kMaxN) return 0;
+    if (check_grid(g) != H4D_OK || check_dtype(table_dt) != H4D_OK || n < 0 || n > kMaxQ) return 0;
     if (table_dt == H4D_F64) return 0;  // the FP64 form runs in one pass
     return input_grad_workspace_bytes(g->L, (int)n);
 }
@@ -333,7 +336,7 @@ static size_t smooth_ws(const h4d_grid* g, h4d_dtype table_dt, int64_t n) {
 }
 
 size_t smoothness_workspace_bytes(const h4d_grid* g, h4d_dtype table_dt, int64_t n) {
-    if (check_grid(g) != H4D_OK || check_dtype(table_dt) != H4D_OK || n < 0 || n > kMaxN) return 0;
+    if (check_grid(g) != H4D_OK || check_dtype(table_dt) != H4D_OK || n < 0 || n > kMaxQ) return 0;
     if (n * (int64_t)g->L * g->F > kMaxN) return 0;
     return smooth_ws(g, table_dt, n);
 }
@@ -421,7 +424,7 @@ h4d_status hash4d_encode_backward_smooth(const h4d_grid* g, h4d_dtype table_dt, 
 }
 
 size_t hash4d_collision_workspace_bytes(const h4d_grid* g, int32_t level, int64_t n) {
-    if (check_grid(g) != H4D_OK || level < 0 || level >= g->L || n < 0 || n > kMaxN) return 0;
+    if (check_grid(g) != H4D_OK || level < 0 || level >= g->L || n < 0 || n > kMaxQ) return 0;
     return census_workspace_bytes(n, g->offset[level + 1] - g->offset[level]);
 }
 
@@ -446,7 +449,7 @@ h4d_status hash4d_collision_census(const h4d_grid* g, int32_t level, const float
 }
 
 size_t hash4d_decompose_workspace_bytes(int64_t n) {
-    if (n < 0 || n > kMaxN) return 0;
+    if (n < 0 || n > kMaxQ) return 0;
     return decompose_workspace_bytes(n);
 }
 
@@ -454,7 +457,7 @@ h4d_status hash4d_decompose(const float* dp, int64_t n, float k_percent, float l
                             int32_t* n_dynamic, uint8_t* is_dynamic, float* loss, float* d_dp, void* workspace,
                             size_t ws_bytes, void* stream) {
     g_last_error.clear();
-    if (n < 0 || n > kMaxN) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-1", (long long)n);
+    if (n < 0 || n > kMaxQ) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-2^16", (long long)n);
     if (!(k_percent >= 0.f && k_percent <= 100.f)) return fail(H4D_EINVAL, "k_percent must be in [0, 100]");
     if (n == 0) return H4D_OK;
     if (!dp) return fail(H4D_EINVAL, "dp is NULL");
@@ -553,14 +556,14 @@ h4d_status h4d_probe_lds_atomic(int32_t blocks, int32_t per_thread, int32_t acti
 }
 
 size_t deform_mlp_workspace_bytes(const h4d_mlp* m, h4d_dtype dt, int64_t n) {
-    if (check_mlp(m, dt) != H4D_OK || n < 0 || n > kMaxN) return 0;
+    if (check_mlp(m, dt) != H4D_OK || n < 0 || n > kMaxQ) return 0;
     return mlp_workspace_bytes(dt, m->in, m->out, (int)n);
 }
 
 // Feature strides of the decoder input for (layout, F); F = 1 for query-major.
 static h4d_status mlp_strides(const h4d_mlp* m, int64_t n, h4d_layout layout, int32_t F, int* Fk, int64_t* ls,
                               int64_t* qs) {
-    if (n < 0 || n > kMaxN) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-1", (long long)n);
+    if (n < 0 || n > kMaxQ) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-2^16", (long long)n);
     if ((int64_t)n * m->in > kMaxN) return fail(H4D_EINVAL, "n in exceeds 2^31-1 features");
     if (layout == H4D_QUERY_MAJOR) {
         *Fk = 1;
@@ -621,7 +624,7 @@ h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* param
 h4d_status hash4d_deform_apply(const float* delta, int64_t n, int32_t out, const float* xyz, const float* rot,
                                const float* scale, float* xyz_out, float* rot_out, float* scale_out, void* stream) {
     g_last_error.clear();
-    if (n < 0 || n > kMaxN) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-1", (long long)n);
+    if (n < 0 || n > kMaxQ) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-2^16", (long long)n);
     if (out < 10 || out > H4D_MAX_OUT) return fail(H4D_EINVAL, "out=%d: the heads need 10 columns", out);
     if (n == 0) return H4D_OK;
     if (!delta || !xyz || !rot || !scale || !xyz_out || !rot_out || !scale_out)
@@ -632,7 +635,7 @@ h4d_status hash4d_deform_apply(const float* delta, int64_t n, int32_t out, const
 }
 
 size_t hash4d_deform_workspace_bytes(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, int64_t n) {
-    if (check_grid(g) != H4D_OK || check_mlp(m, dt) != H4D_OK || n < 0 || n > kMaxN) return 0;
+    if (check_grid(g) != H4D_OK || check_mlp(m, dt) != H4D_OK || n < 0 || n > kMaxQ) return 0;
     return deform_ws(g, m, dt, n);
 }
 

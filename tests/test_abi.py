@@ -193,3 +193,34 @@ def test_entry_points_validate_without_launching():
     assert lib.deform_mlp_backward(mp, 0, fake, fake, 0, OW, 0, fake, 1.0, 1.0, fake, None, fake, 8, None) == -1
     assert lib.deform_mlp_backward(mp, 0, fake, fake, 0, 0, 0, fake, 1.0, 1.0, fake, None, fake, 8, None) == 0
     assert lib.deform_mlp_forward(mp, 0, fake, fake, 5, OW, 0, fake, None) == -1            # no gradient there
+
+
+def test_query_count_limit_boundary():
+    """n up to 2^31 - 2^16 passes the size checks (validation then stops at a NULL
+    pointer, before any launch); one more query is rejected as out of range, so no
+    kernel sees a count whose padding to whole workgroups overflows 32 bits."""
+    lib = _lib.load()
+    limit = (1 << 31) - (1 << 16)
+    g = _lib.h4d_grid_init(1, 1, [4], [4], 1 << 12)
+    gp = _lib.ctypes.byref(g)
+    fake = 1 << 20
+    assert lib.hash4d_encode(gp, 0, None, fake, limit, 0, fake, None) == -1
+    assert "NULL" in _lib.last_error()
+    assert lib.hash4d_encode(gp, 0, None, fake, limit + 1, 0, fake, None) == -1
+    assert "outside" in _lib.last_error()
+    assert _lib.hash4d_encode_backward_workspace_bytes(g, limit) > 0
+    assert _lib.hash4d_encode_backward_workspace_bytes(g, limit + 1) == 0
+    m = _lib.mlp_shape(8)
+    mp = _lib.ctypes.byref(m)
+    lim8 = ((1 << 31) - 1) // 8   # n in <= 2^31 - 1 features binds first for in = 8
+    assert lib.deform_mlp_forward(mp, 0, None, fake, lim8, 0, 0, fake, None) == -1
+    assert "NULL" in _lib.last_error()
+    assert lib.deform_mlp_forward(mp, 0, None, fake, limit + 1, 0, 0, fake, None) == -1
+    assert "outside" in _lib.last_error()
+    assert lib.hash4d_decompose(None, limit, 10.0, 1.0, None, None, None, None, None, fake, 1 << 20, None) == -1
+    assert "dp" in _lib.last_error()
+    assert lib.hash4d_decompose(fake, limit + 1, 10.0, 1.0, None, None, None, None, None, fake, 1 << 20,
+                                None) == -1
+    assert "outside" in _lib.last_error()
+    assert lib.hash4d_deform_apply(None, limit + 1, 10, fake, fake, fake, fake, fake, fake, None) == -1
+    assert "outside" in _lib.last_error()
