@@ -66,11 +66,11 @@ def source_hash() -> str:
 class Path:
     """Device buffers and the step of one form (fp32 or bf16) of the workload."""
 
-    def __init__(self, torch, _lib, synth, form: str, n: int | None = None):
+    def __init__(self, torch, _lib, synth, form: str, n: int | None = None, shared_frame: int | None = None):
         self.torch, self.L_, self.form = torch, _lib, form
         w = synth.PAPER_SCENE
         self.w = w
-        rng, x = synth.scene_inputs(w.n if n is None else n, 0)
+        rng, x = synth.scene_inputs(w.n if n is None else n, 0, shared_frame=shared_frame)
         rs = _lib.h4d_grid_schedule(w.L, *w.space)
         rt = _lib.h4d_grid_schedule(w.L, *w.time)
         self.g = _lib.h4d_grid_init(w.L, w.F, rs, rt, w.T)
@@ -646,6 +646,13 @@ def main():
                                 "vs_fp32": form_differences(ref32, bf)},
                        "smoothness": smooth}
     del bf, ref32
+    torch.cuda.empty_cache()
+    # every query at frame 150 of 300: one view per training iteration
+    sh = Path(torch, _lib, synth, "fp32", shared_frame=150)
+    wall_s, _, per_s = sh.run(args.steps, args.warmup)
+    result["forms"]["shared_t"] = {"value": n * args.steps / wall_s, "ms_per_step": wall_s * 1e3 / args.steps,
+                                   "kernels_ms": per_s, "frame": 150, "form": "fp32"}
+    del sh
     torch.cuda.empty_cache()
     if not args.no_batched:
         result["forms"]["batched"] = batched_form(torch, _lib, synth, max(3, args.steps // 5), 2)

@@ -184,6 +184,85 @@ def test_batched_bf16_with_masters_and_loss_scale():
         f_ref, d_ref = O.deform_forward(xt, s["table"], s["og"], s["params"])
         fs = O.encode(xt, np.abs(s["table"]), s["og"])
         scaled_close(host(s["delta"])[k], d_ref, mlp_forward_scale(s["params"], fs), RTOL_BF16, "bf16 delta")
+        # loss-scaled BF16 gradients (d_delta times 1024 on load, 1/1024 on the way out)
+        # against the oracle on the FP32 masters
+        rt, rp, st, sp = oracle_grads(s)
+        scaled_close(host(s["d_table"]), rt, st, RTOL_BF16, "bf16 batched d_table")
+        scaled_close(host(s["d_params"]), rp, sp, RTOL_BF16, "bf16 batched d_params")
+    plan.destroy()
+
+
+def test_batched_bf16_multi_scene_workload_sampled():
+    """The multi-scene workload at its own shape: 8 clustered scenes of 50k .. 1.2M
+    Gaussians (seed = scene index), T = 2^17 / 2^18 / 2^19 by scene size, L = 16, F = 2,
+    the paper scene's schedule and 32-64-64-10 decoder, 4 timestamps (frames 0, 99,
+    199, 299), BF16 tables and decoders rounded from FP32 masters inside the captured
+    step, loss scale 4096.  The upstream gradient is zero except on 4096 sampled
+    queries per (scene, timestamp), so the whole d_table and d_params equal the
+    oracle's sums over the samples (zero rows contribute exact zeros); feat and delta
+    are compared on the samples."""
+    import torch
+    w = synth.PAPER_SCENE
+    rs = O.level_resolutions(*w.space, w.L)
+    rt_ = O.level_resolutions(*w.time, w.L)
+    times = synth.BATCHED_TIMES
+    nt = len(times)
+    scenes, descriptors = [], []
+    for i, n in enumerate(synth.BATCHED_SCENE_N):
+        rng = np.random.default_rng(i)
+        xyz = synth.clustered_xyz(n, rng)
+        x4 = np.concatenate([xyz, np.zeros((n, 1), np.float32)], axis=1)
+        T = 1 << synth.batched_table_rows_log2(n)
+        og = O.make_grid(w.L, w.F, rs, rt_, T)
+        lg = _lib.h4d_grid_init(w.L, w.F, rs, rt_, T)
+        assert lg.offsets() == og.offsets
+        table = synth.table_init(og.E, w.F, rng)
+        params = synth.decoder_params(w.n_in, rng)
+        samples = [np.sort(rng.choice(n, 4096, replace=False)) for _ in range(nt)]
+        gd = np.zeros((nt, n, 10), np.float32)
+        for k in range(nt):
+            gd[k, samples[k]] = synth.upstream(4096, 10, rng)
+        s = {"n": n, "og": og, "x": x4, "table": table, "params": params, "gd": gd, "samples": samples,
+             "xyz_d": dev(x4), "table_m": dev(table), "params_m": dev(params),
+             "table_d": torch.empty(table.size, dtype=torch.int16, device="cuda"),
+             "params_d": torch.empty(params.size, dtype=torch.int16, device="cuda"),
+             "feat": torch.full((nt, w.L, n, w.F), float("nan"), device="cuda"),
+             "delta": torch.full((nt, n, 10), float("nan"), device="cuda"), "gd_d": dev(gd),
+             "d_table": torch.full((og.E, w.F), float("nan"), device="cuda"),
+             "d_params": torch.full((params.size,), float("nan"), device="cuda")}
+        scenes.append(s)
+        descriptors.append(_lib.scene_desc(lg, n, s["xyz_d"], times, s["table_d"], s["params_d"], s["feat"],
+                                           s["delta"], s["gd_d"], s["d_table"], s["d_params"],
+                                           table_master=s["table_m"], params_master=s["params_m"]))
+    plan = _lib.BatchedPlan(descriptors, _lib.mlp_shape(w.n_in), _lib.BF16, 4096.0,
+                            _lib.PLAN_AUTOTUNE | _lib.PLAN_GRAPH | _lib.PLAN_ZERO_GRADS)
+    info = plan.info()
+    assert info.queries == 4 * sum(synth.BATCHED_SCENE_N) and info.graph == 1
+    plan.run()
+    for i, s in enumerate(scenes):
+        og, table, params = s["og"], s["table"], s["params"]
+        feat, delta = host(s["feat"]), host(s["delta"])
+        rt = np.zeros((og.E, og.F))
+        rp = np.zeros(params.size)
+        st, sp = np.zeros_like(rt), np.zeros_like(rp)
+        for k, t in enumerate(times):
+            idx = s["samples"][k]
+            xt = s["x"][idx].copy()
+            xt[:, 3] = np.float32(t)
+            f_ref, d_ref = O.deform_forward(xt, table, og, params)
+            f_scale = O.encode(xt, np.abs(table), og)
+            got_f = np.transpose(feat[k][:, idx], (1, 0, 2)).reshape(len(idx), -1)
+            scaled_close(got_f, f_ref, f_scale, RTOL_BF16, f"scene {i} t {k} feat")
+            scaled_close(delta[k][idx], d_ref, mlp_forward_scale(params, f_scale), RTOL_BF16,
+                         f"scene {i} t {k} delta")
+            a, b, _ = O.deform_backward(xt, table, og, params, s["gd"][k][idx])
+            sf, spk = mlp_backward_scale(params, f_ref, s["gd"][k][idx])
+            rt += a
+            rp += b
+            st += O.encode_backward(xt, sf, og)
+            sp += spk
+        scaled_close(host(s["d_table"]), rt, st, RTOL_BF16, f"scene {i} d_table")
+        scaled_close(host(s["d_params"]), rp, sp, RTOL_BF16, f"scene {i} d_params")
     plan.destroy()
 
 

@@ -281,16 +281,24 @@ def test_encode_backward_overwrite(dt):
     assert (host(d) == 0).all()
 
 
-def test_encode_backward_paper_scene_full_size_property():
-    # At n = 200k: <u, d_table> = <G(u), g> for random u (the backward is the exact
-    # transpose of the forward), with G(u) evaluated by the oracle on every query.
+# The configuration the benchmark times (n = 200k clustered queries, L = 16, T = 2^19),
+# with each query at its own frame and with every query at frame 150 of 300 (one
+# view per training iteration): the whole table gradient, row by row, against the
+# oracle's transpose of Eq. 9, plus the transpose identity <u, d_table> = <G(u), g>.
+@pytest.mark.parametrize("shared", [None, 150], ids=["own-frames", "shared-frame-150"])
+def test_encode_backward_paper_scene_full_size_elementwise(shared):
     w = synth.PAPER_SCENE
-    og, lg, x, _, rng = encoder_case(w, w.n, 10, edges=False)
+    og, lg = oracle_grid(w), lib_grid(w)
+    assert_same_layout(og, lg)
+    rng, x = synth.scene_inputs(w.n, 10, shared_frame=shared)
     gf = synth.upstream(w.n, og.L * og.F, rng)
     d_table = run_backward(lg, _lib.F32, x, gf, og.E).astype(np.float64)
+    ref = O.encode_backward(x, gf, og)
+    scaled_close(d_table, ref, O.encode_backward(x, np.abs(gf), og), RTOL_GRAD, "d_table 200k")
+    # rows no corner reaches stay exactly zero
+    assert not np.any(d_table[np.all(ref == 0, axis=1)])
     u = rng.standard_normal((og.E, og.F))
     lhs = float(np.sum(u * d_table))
-    fu = O.encode(x, u, og)
-    rhs = float(np.sum(fu * gf))
+    rhs = float(np.sum(O.encode(x, u, og) * gf))
     scale = float(np.sum(O.encode(x, np.abs(u), og) * np.abs(gf)))
     assert abs(lhs - rhs) <= RTOL_GRAD * scale
