@@ -147,6 +147,21 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
                                   h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
                                   void* workspace, size_t ws_bytes, void* stream);
 
+/* hash4d_encode_backward without a workspace argument and without any device
+ * allocation, for callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments (minus
+ * workspace / ws_bytes), kernels and results as hash4d_encode_backward.  The tile
+ * masks go to a static workspace of 64 MiB (67108864 bytes) per GPU, a file-scope
+ * device array that each GPU holds from the library's load until the process ends;
+ * a call whose hash4d_encode_backward_workspace_bytes(g, n) exceeds it returns
+ * H4D_EINVAL and launches nothing.  No call reads what an earlier call left there.
+ * Every call on one GPU shares that array: calls that overlap on one GPU (two
+ * streams, or two host threads, without ordering between them) race and give wrong
+ * gradients, so the caller orders them. */
+h4d_status hash4d_encode_backward_noalloc(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
+                                          h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
+                                          void* stream);
+
 /* Gradient of the encoder with respect to its input positions, for callers that
  * learn the canonical positions through the encoder (the derivative of Eq. 9):
  *   d_xyzt[q, d] += grad_scale * sum_l sum_f d_feat[q, l F + f] * d f_h[l F + f] / d x_d

@@ -97,6 +97,7 @@ SIGNATURES = {
     "hash4d_encode": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _P]),
     "hash4d_encode_backward_workspace_bytes": (_SZ, [_GP, _I64]),
     "hash4d_encode_backward": (_I32, [_GP, _I32, _P, _I64, _I32, _P, _F32, _P, _P, _SZ, _P]),
+    "hash4d_encode_backward_noalloc": (_I32, [_GP, _I32, _P, _I64, _I32, _P, _F32, _P, _P]),
     "hash4d_encode_backward_input_workspace_bytes": (_SZ, [_GP, _I32, _I64]),
     "hash4d_encode_backward_input": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _F32, _P, _P, _SZ, _P]),
     "hash4d_corner_indices": (_I32, [_GP, _P, _I64, _P, _P, _P]),
@@ -217,6 +218,13 @@ def hash4d_encode_backward(g: Grid, grad_dt: int, xyzt, n: int, d_feat, grad_sca
     _check("hash4d_encode_backward",
            load().hash4d_encode_backward(ctypes.byref(g), grad_dt, ptr(xyzt), n, layout, ptr(d_feat), grad_scale,
                                          ptr(d_table), ptr(workspace), ws_bytes, stream_handle(stream)))
+
+
+def hash4d_encode_backward_noalloc(g: Grid, grad_dt: int, xyzt, n: int, d_feat, grad_scale: float, d_table,
+                                   layout: int = QUERY_MAJOR, stream=None) -> None:
+    _check("hash4d_encode_backward_noalloc",
+           load().hash4d_encode_backward_noalloc(ctypes.byref(g), grad_dt, ptr(xyzt), n, layout, ptr(d_feat),
+                                                 grad_scale, ptr(d_table), stream_handle(stream)))
 
 
 def hash4d_encode_backward_input_workspace_bytes(g: Grid, table_dt: int, n: int) -> int:

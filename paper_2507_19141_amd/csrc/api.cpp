@@ -253,9 +253,13 @@ size_t hash4d_encode_backward_workspace_bytes(const h4d_grid* g, int64_t n) {
     return scatter_mask_bytes((int)n, g->L);
 }
 
-h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
-                                  h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
-                                  void* workspace, size_t ws_bytes, void* stream) {
+// Validation and launch shared by hash4d_encode_backward and its static-workspace
+// form.  static_ws: the masks go to the library's static array (static_scratch)
+// instead of `workspace`.
+static h4d_status encode_backward_call(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
+                                       h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
+                                       void* workspace, size_t ws_bytes, bool static_ws, void* stream,
+                                       const char* where) {
     g_last_error.clear();
     h4d_status st;
     int64_t ls, qs;
@@ -268,19 +272,40 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
     if (n == 0) {  // no query: the written gradient is zero
         if (!d_table) return fail(H4D_EINVAL, "d_table is NULL");
         const int64_t words = g->offset[g->L] * g->F * (grad_dt == H4D_F64 ? 2 : 1);
-        return hip_status(launch_zero_words(d_table, words, (hipStream_t)stream), "hash4d_encode_backward");
+        return hip_status(launch_zero_words(d_table, words, (hipStream_t)stream), where);
     }
     if (!d_feat || !d_table) return fail(H4D_EINVAL, "d_feat or d_table is NULL");
     const size_t need = scatter_mask_bytes((int)n, g->L);
-    if (!workspace || ws_bytes < need)
-        return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
-    if (((uintptr_t)workspace) & 15u) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
+    if (static_ws) {
+        if (need > kStaticScratchBytes)
+            return fail(H4D_EINVAL, "n=%lld, L=%d need %zu bytes of workspace; the static workspace holds %zu",
+                        (long long)n, g->L, need, kStaticScratchBytes);
+        if ((st = hip_status(static_scratch(&workspace), where))) return st;
+    } else {
+        if (!workspace || ws_bytes < need)
+            return fail(H4D_EINVAL, "workspace of %zu bytes, %zu needed", workspace ? ws_bytes : (size_t)0, need);
+        if (((uintptr_t)workspace) & 15u) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
+    }
     const DevGrid d = to_device(*g);
     int64_t rows[H4D_MAX_LEVELS];
     rows_of(*g, rows);
     return hip_status(launch_scatter_tiled(d, rows, grad_dt, xyzt, nullptr, (int)n, d_feat, ls, qs,
                                            (double)grad_scale, d_table, workspace, (hipStream_t)stream, overwrite),
-                      "hash4d_encode_backward");
+                      where);
+}
+
+h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
+                                  h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
+                                  void* workspace, size_t ws_bytes, void* stream) {
+    return encode_backward_call(g, grad_dt, xyzt, n, layout, d_feat, grad_scale, d_table, workspace, ws_bytes,
+                                false, stream, "hash4d_encode_backward");
+}
+
+h4d_status hash4d_encode_backward_noalloc(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
+                                          h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
+                                          void* stream) {
+    return encode_backward_call(g, grad_dt, xyzt, n, layout, d_feat, grad_scale, d_table, nullptr, 0, true, stream,
+                                "hash4d_encode_backward_noalloc");
 }
 
 size_t hash4d_encode_backward_input_workspace_bytes(const h4d_grid* g, h4d_dtype table_dt, int64_t n) {

@@ -6,6 +6,8 @@
 // instead of every XCD streaming the whole table through its L2.
 #include <string.h>
 
+#include <mutex>
+
 #include "h4d_device.h"
 
 namespace h4d {
@@ -321,6 +323,33 @@ hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d
                                       main, s)
                : tiled_g<float, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, overwrite,
                                        main, s);
+}
+
+// ------------------------------------------ static workspace (no allocation) ----
+// The tile masks of hash4d_encode_backward_noalloc live in this file-scope array:
+// each GPU holds its own copy from module load until the process ends, and every
+// call on that GPU shares it.  On the host the array's name is only a stand-in, not
+// a device address: its address on the current device is looked up once per device
+// with hipGetSymbolAddress and cached, and only that address is ever passed on.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void** ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w, hipStream_t s) {

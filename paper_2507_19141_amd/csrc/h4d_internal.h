@@ -73,6 +73,10 @@ hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d
                                 const float* eps, int n, const void* src, int64_t lstride, int64_t qstride,
                                 double scale, void* d_table, void* mask_ws, hipStream_t s, bool overwrite = false,
                                 const MainGradArg& main = MainGradArg{});
+// The static workspace of hash4d_encode_backward_noalloc: kStaticScratchBytes of
+// device memory per GPU (a file-scope array), its address on the current device.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+hipError_t static_scratch(void** ptr);
 hipError_t launch_corner_indices(const DevGrid& g, const float* xyzt, int n, int32_t* rows, float* w,
                                  hipStream_t s);
 // Fused Adam step + optional BF16 copy + gradient zeroing (optim.hip); row in {1,2,4,8}.
