@@ -15,9 +15,12 @@ namespace h4d {
 
 constexpr int kDecBlock = 256;
 
+// (x^2 + y^2) + z^2 in FP32, each product and sum rounded on its own: contraction is
+// off in this block, so no step becomes a fused multiply-add.
 __device__ __forceinline__ uint32_t motion_key(const float* __restrict__ dp, int64_t i) {
+#pragma clang fp contract(off)
     const float x = dp[3 * i], y = dp[3 * i + 1], z = dp[3 * i + 2];
-    const float s = __fadd_rn(__fadd_rn(__fmul_rn(x, x), __fmul_rn(y, y)), __fmul_rn(z, z));
+    const float s = (x * x + y * y) + z * z;
     return __float_as_uint(s);
 }
 

@@ -72,11 +72,21 @@ __global__ __launch_bounds__(kEncodeBlock) void k_encode(DevGrid g, const TT* __
 template <bool PAIR>
 __global__ __launch_bounds__(kEncodeBlock) void k_tile_mask(DevGrid g, TileMap tm, const float4* __restrict__ xyzt,
                                                             const float4* __restrict__ eps, int n,
-                                                            uint32_t* __restrict__ mask) {
+                                                            uint32_t* __restrict__ mask, uint2* __restrict__ words) {
     const int l = blockIdx.y;
     const int q = blockIdx.x * kEncodeBlock + threadIdx.x;
     if (q >= n) return;
     const float4 x = xyzt[q];
+    if (!PAIR && ((tm.pair_words >> l) & 1u)) {
+        const uint2 b = pair_tile_bytes(g, tm, l, level_cell(g, l, x));
+        const int bs = tm.bit_shift[l];
+        uint32_t m = 0;
+#pragma unroll
+        for (int k = 0; k < 32; k += 8) m |= (1u << (((b.x >> k) & 0xffu) >> bs)) | (1u << (((b.y >> k) & 0xffu) >> bs));
+        mask[(int64_t)l * mask_stride(n) + q] = m;
+        words[(int64_t)l * mask_stride(n) + q] = b;
+        return;
+    }
     uint32_t m = corner_tile_mask(g, tm, l, x);
     if constexpr (PAIR) {
         const float4 e = eps[q];
@@ -154,15 +164,99 @@ __device__ __forceinline__ void tile_run(const DevGrid& g, const TileMap& tm, in
     }
 }
 
+// Levels with per-pair tile bytes (tm.pair_words): a queued query usually has one
+// pair in the tile, sometimes two or more.  Every lane adds the first of its pairs at
+// once; a query with more goes to a per-wavefront overflow queue (query, remaining
+// pairs), which is worked off a full wavefront at a time, so no lane idles through
+// another lane's extra pairs.
+template <typename G, int F>
+struct WordQuery {
+    float4 x;
+    G gv[F];
+    uint2 wd;
+    int q;
+};
+
+constexpr int kOverflowCap = 128;  // entries per wavefront
+
+template <typename G, int F>
+__device__ __forceinline__ void scatter_pair_words(const DevGrid& g, const TileMap& tm, int l, uint32_t tau,
+                                                   uint32_t bit, const float4* __restrict__ xyzt, int n,
+                                                   const uint32_t* __restrict__ lmask, const uint2* __restrict__ lwords,
+                                                   const G* __restrict__ src, int64_t lstride, int64_t qstride,
+                                                   G scale, int* queue, int2* overflow, G* tile) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int2* ovf = overflow + (threadIdx.x >> 6) * kOverflowCap;
+    const uint32_t rmask = (1u << tm.tile_shift[l]) - 1u;
+    const G* gl = src + (int64_t)l * lstride;
+    int ovn = 0;  // entries in this wavefront's overflow queue (wavefront-uniform)
+    // whole wavefront: add the first pair of pm (none if pm = 0), queue the rest
+    auto visit = [&](float4 x, const G (&gv)[F], uint32_t pm, int q) {
+        const uint32_t rest = pm & (pm - 1u);
+        const uint64_t bal = __ballot(rest != 0u);
+        if (rest) ovf[ovn + __popcll(bal & below)] = make_int2(q, (int)rest);
+        ovn += (int)__popcll(bal);
+        wave_sync();
+        if (pm) pair_contrib<G, F>(g, l, x, __builtin_ctz(pm), gv, rmask, tile);
+    };
+    // work off the overflow queue while it holds more than `keep` entries
+    auto drain = [&](int keep) {
+        while (ovn > keep) {
+            const int take = min(ovn, 64);
+            const int2 e = lane < take ? ovf[lane] : make_int2(0, 0);
+            const int rest = ovn - take;
+            const int2 moved = lane < rest ? ovf[64 + lane] : make_int2(0, 0);
+            wave_sync();
+            if (lane < rest) ovf[lane] = moved;
+            wave_sync();
+            ovn = rest;
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            G gv[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) gv[f] = G(0);
+            if (lane < take) {
+                x = xyzt[e.x];
+                const G* gp = gl + (int64_t)e.x * qstride;
+#pragma unroll
+                for (int f = 0; f < F; ++f) gv[f] = gp[f] * scale;
+            }
+            visit(x, gv, lane < take ? (uint32_t)e.y : 0u, e.x);
+        }
+    };
+    masked_queue_loop_wave<kScatterBlock>(
+        n, lmask, bit, queue,
+        [&](int q) {
+            WordQuery<G, F> t;
+            const G* gp = gl + (int64_t)q * qstride;
+#pragma unroll
+            for (int f = 0; f < F; ++f) t.gv[f] = gp[f];
+            t.x = xyzt[q];
+            t.wd = lwords[q];
+            t.q = q;
+            return t;
+        },
+        [&](const WordQuery<G, F>& t, bool active) {
+            G gv[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) gv[f] = t.gv[f] * scale;
+            visit(t.x, gv, active ? pair_hits(t.wd, tau) : 0u, t.q);
+            drain(63);
+        });
+    drain(0);
+}
+
 template <typename G, int F, bool PAIR>
 __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, TileMap tm, const float4* __restrict__ xyzt,
                                                                 const float4* __restrict__ eps, int n,
                                                                 const uint32_t* __restrict__ mask,
+                                                                const uint2* __restrict__ words,
                                                                 const G* __restrict__ src, int64_t lstride,
                                                                 int64_t qstride, G scale, G* __restrict__ d_table,
                                                                 int overwrite, MainGrad<G> mg) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int queue[kQueueCap];
+    __shared__ int2 overflow[PAIR ? 1 : kScatterBlock / 64 * kOverflowCap];
     G* tile = reinterpret_cast<G*>(smem);
     int l = 0;
     while (l + 1 < g.L && (int)blockIdx.x >= tm.tile_start[l + 1]) ++l;
@@ -173,10 +267,16 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
     const uint32_t bit = tile_bit(tm, l, first);
     for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) tile[i] = G(0);
     __syncthreads();
-    masked_queue_loop<kScatterBlock>(
-        n, mask + (int64_t)l * mask_stride(n), bit, queue,
-        [&](int q) { return tile_load<G, F, PAIR>(l, xyzt, eps, src, lstride, qstride, mg, q); },
-        [&](const TileQuery<G, F, PAIR>& t) { tile_run<G, F, PAIR>(g, tm, l, t, scale, mg, base, cnt, tile); });
+    if (!PAIR && ((tm.pair_words >> l) & 1u)) {
+        scatter_pair_words<G, F>(g, tm, l, t_in_level, bit, xyzt, n, mask + (int64_t)l * mask_stride(n),
+                                 words + (int64_t)l * mask_stride(n), src, lstride, qstride, scale, queue, overflow,
+                                 tile);
+    } else {
+        masked_queue_loop<kScatterBlock>(
+            n, mask + (int64_t)l * mask_stride(n), bit, queue,
+            [&](int q) { return tile_load<G, F, PAIR>(l, xyzt, eps, src, lstride, qstride, mg, q); },
+            [&](const TileQuery<G, F, PAIR>& t) { tile_run<G, F, PAIR>(g, tm, l, t, scale, mg, base, cnt, tile); });
+    }
     __syncthreads();
     // the tile's rows have no other owner: add them to d_table, or with overwrite set
     // write every row (the tiles of the levels cover all E rows)
@@ -247,7 +347,7 @@ hipError_t launch_encode(const DevGrid& g, h4d_dtype dt, const void* table, cons
 }
 
 // Tiles of at most 128 KiB of LDS; tile_start is the first tile of each level.
-TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes) {
+TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes, bool pair_words) {
     TileMap tm;
     memset(&tm, 0, sizeof tm);
     tm.max_rows = kTileBytes / (F * gbytes);  // a power of two: F and gbytes are
@@ -264,6 +364,7 @@ TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gb
             2 * (int64_t)g.res_s[l] <= ((int64_t)1 << sh))
             tm.pair_cotiled |= 1u << l;
         const int P = (int)((level_rows[l] + (1 << sh) - 1) >> sh);
+        if (pair_words && ((tm.pair_cotiled >> l) & 1u) && P <= 256) tm.pair_words |= 1u << l;
         while (((P - 1) >> tm.bit_shift[l]) >= 32) ++tm.bit_shift[l];
         t += P;
     }
@@ -271,18 +372,18 @@ TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gb
     return tm;
 }
 
-size_t scatter_mask_bytes(int n, int L) { return (size_t)mask_stride(n) * L * sizeof(uint32_t); }
+size_t scatter_mask_bytes(int n, int L) { return (size_t)mask_stride(n) * L * (sizeof(uint32_t) + sizeof(uint2)); }
 
 template <typename G, int F, bool PAIR>
 static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt, const float* eps, int n,
-                          const uint32_t* mask, const void* src, int64_t ls, int64_t qs, double scale, void* d_table,
-                          bool overwrite, const MainGradArg& main, hipStream_t s) {
+                          const uint32_t* mask, const uint2* words, const void* src, int64_t ls, int64_t qs,
+                          double scale, void* d_table, bool overwrite, const MainGradArg& main, hipStream_t s) {
     auto kern = k_scatter_tiled<G, F, PAIR>;
     const size_t lds = (size_t)tm.max_rows * F * sizeof(G);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(tm.tile_start[g.L]), dim3(kScatterBlock), lds, s, g, tm,
-                       reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n, mask,
+                       reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n, mask, words,
                        static_cast<const G*>(src), ls, qs, (G)scale, static_cast<G*>(d_table), overwrite ? 1 : 0,
                        MainGrad<G>{static_cast<const G*>(main.src), main.lstride, main.qstride, (G)main.scale});
     return hipGetLastError();
@@ -292,18 +393,23 @@ template <typename G, bool PAIR>
 static hipError_t tiled_g(const DevGrid& g, const int64_t* level_rows, const float* xyzt, const float* eps, int n,
                           const void* src, int64_t ls, int64_t qs, double scale, void* d_table, void* mask_ws,
                           bool overwrite, const MainGradArg& main, hipStream_t s) {
-    const TileMap tm = make_tile_map(g, level_rows, g.F, (int)sizeof(G));
+    const TileMap tm = make_tile_map(g, level_rows, g.F, (int)sizeof(G), !PAIR);
     uint32_t* mask = static_cast<uint32_t*>(mask_ws);
+    uint2* words = reinterpret_cast<uint2*>(mask + mask_stride(n) * g.L);
     hipLaunchKernelGGL(k_tile_mask<PAIR>, dim3((unsigned)((n + kEncodeBlock - 1) / kEncodeBlock), (unsigned)g.L),
                        dim3(kEncodeBlock), 0, s, g, tm, reinterpret_cast<const float4*>(xyzt),
-                       reinterpret_cast<const float4*>(eps), n, mask);
+                       reinterpret_cast<const float4*>(eps), n, mask, words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (g.F) {
-        case 1: return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, main, s);
-        case 2: return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, main, s);
-        case 4: return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, main, s);
-        case 8: return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, mask, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 1:
+            return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, mask, words, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 2:
+            return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, mask, words, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 4:
+            return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, mask, words, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 8:
+            return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, mask, words, src, ls, qs, scale, d_table, overwrite, main, s);
     }
     return hipErrorInvalidValue;
 }

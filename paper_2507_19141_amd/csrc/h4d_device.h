@@ -34,10 +34,13 @@ __device__ __forceinline__ float clamp_unit(float x) {
 }
 
 // Lower vertex and fractional offset along one dimension: pos = x * N rounded once
-// in FP32 (__fmul_rn keeps it out of any fused multiply-add), i = min(floor(pos),
-// N - 1), frac = pos - i, which is exact in FP32.
+// in FP32, i = min(floor(pos), N - 1), frac = pos - i, which is exact in FP32.
+// Contraction is off in this block: the compiler would otherwise fuse the product
+// into the subtraction (frac = fma(x, N, -i)), skipping the rounding of pos that the
+// floor saw, and the weights would no longer be those of the cell the indices name.
 __device__ __forceinline__ void cell_1d(float x, int N, int& i, float& fr) {
-    const float pos = __fmul_rn(x, (float)N);
+#pragma clang fp contract(off)
+    const float pos = x * (float)N;
     i = min((int)floorf(pos), N - 1);
     fr = pos - (float)i;
 }
@@ -385,6 +388,55 @@ __device__ __forceinline__ uint32_t corner_tile_mask(const DevGrid& g, const Til
     return m;
 }
 
+// ---- per-pair tile bytes (levels whose x-pairs share a tile, tm.pair_words) ----
+// On such a level the tile of pair p = (dy, dz, dt) (bits 0, 1, 2 of p) depends only
+// on the y, z and t terms of Eq. 8: the x term is below the tile's row bits.  The
+// mask pass stores each pair's tile index (at most 255) in byte p of a 64-bit word
+// (pairs 0-3 in .x, 4-7 in .y), so that a tile workgroup finds a query's pairs in
+// its tile without hashing them again.
+__device__ __forceinline__ uint2 pair_tile_bytes(const DevGrid& g, const TileMap& tm, int l, const Cell& c) {
+    const uint32_t hy0 = (uint32_t)c.iy * g.prime[1], hy1 = hy0 + g.prime[1];
+    const uint32_t hz0 = (uint32_t)c.iz * g.prime[2], hz1 = hz0 + g.prime[2];
+    const uint32_t ht0 = (uint32_t)c.it * g.prime[3], ht1 = ht0 + g.prime[3];
+    const uint32_t sh = (uint32_t)tm.tile_shift[l];
+    uint32_t b[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+        b[p] = ((((p & 1) ? hy1 : hy0) ^ ((p & 2) ? hz1 : hz0) ^ ((p & 4) ? ht1 : ht0)) & g.tmask) >> sh;
+    return make_uint2(b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24), b[4] | (b[5] << 8) | (b[6] << 16) | (b[7] << 24));
+}
+
+// Bit p set iff byte p of wd equals tau (tau < 256): the query's pairs in tile tau.
+__device__ __forceinline__ uint32_t pair_hits(uint2 wd, uint32_t tau) {
+    const uint32_t rep = tau * 0x01010101u;
+    const uint32_t lo = wd.x ^ rep, hi = wd.y ^ rep;
+    // exact zero-byte test: bit 7 of a byte ends up set iff the byte is zero
+    const uint32_t zl = ~(((lo & 0x7f7f7f7fu) + 0x7f7f7f7fu) | lo) & 0x80808080u;
+    const uint32_t zh = ~(((hi & 0x7f7f7f7fu) + 0x7f7f7f7fu) | hi) & 0x80808080u;
+    // gather bits 7, 15, 23, 31 into bits 24..27 (the partial products cannot carry there)
+    return (((zl >> 7) * 0x01020408u) >> 24) | ((((zh >> 7) * 0x01020408u) >> 24) << 4);
+}
+
+// Add w_c gv at both corners of x-pair p of x (same y, z, t; lower and upper x) on a
+// level whose pairs share a tile; rmask = tile rows - 1 (tiles are aligned powers of
+// two, so a row's place in its tile is its low bits).
+template <typename G, int F>
+__device__ __forceinline__ void pair_contrib(const DevGrid& g, int l, float4 x, int p, const G (&gv)[F], uint32_t rmask,
+                                             G* tile) {
+    const Cell c = level_cell(g, l, x);
+    const uint32_t dy = (uint32_t)p & 1u, dz = ((uint32_t)p >> 1) & 1u, dt = ((uint32_t)p >> 2) & 1u;
+    const uint32_t H = (((uint32_t)c.iy + dy) * g.prime[1]) ^ (((uint32_t)c.iz + dz) * g.prime[2]) ^
+                       (((uint32_t)c.it + dt) * g.prime[3]);
+    const uint32_t r0 = ((uint32_t)c.ix ^ H) & rmask;  // pi_1 = 1
+    const uint32_t r1 = (((uint32_t)c.ix + 1u) ^ H) & rmask;
+    const G wy = dy ? G(c.fy) : G(1) - G(c.fy);
+    const G wz = dz ? G(c.fz) : G(1) - G(c.fz);
+    const G wt = dt ? G(c.ft) : G(1) - G(c.ft);
+    const G w = (wy * wz) * wt;
+    lds_add_row<G, F>(tile + r0 * F, gv, (G(1) - G(c.fx)) * w);
+    lds_add_row<G, F>(tile + r1 * F, gv, G(c.fx) * w);
+}
+
 // Orders one wavefront's LDS queue writes before its reads by other lanes.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -448,6 +500,60 @@ __device__ __forceinline__ void masked_queue_loop(int n, const uint32_t* __restr
     if (tail) last = load(queue[lane]);
     if (have) run(pend);
     if (tail) run(last);
+}
+
+// As masked_queue_loop, but run(s, active) is always called by the whole wavefront
+// (active is false for the lanes of a partial last batch), so that run may use
+// wavefront-wide operations.
+template <int BLOCK, typename Load, typename Run>
+__device__ __forceinline__ void masked_queue_loop_wave(int n, const uint32_t* __restrict__ lmask, uint32_t bit,
+                                                       int* wqueue, Load load, Run run) {
+    static_assert(BLOCK % 64 == 0, "whole wavefronts");
+    using S = decltype(load(0));
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int* queue = wqueue + wave * 128;
+    const uint4* __restrict__ m4 = reinterpret_cast<const uint4*>(lmask);
+    const int groups = (n + 3) >> 2;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int qn = 0;
+    bool have = false;
+    S pend{};
+    int gi = wave * 64 + lane;
+    uint4 cur = gi < groups ? m4[gi] : make_uint4(0u, 0u, 0u, 0u);
+    for (int g0 = wave * 64; g0 < groups; g0 += BLOCK) {
+        const int gn = gi + BLOCK;
+        const uint4 nxt = gn < groups ? m4[gn] : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t mm[4] = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = 4 * gi + j;
+            const bool hit = (mm[j] & bit) != 0u && q < n;
+            const uint64_t bal = __ballot(hit);
+            if (hit) queue[qn + __popcll(bal & below)] = q;
+            qn += (int)__popcll(bal);
+            wave_sync();
+            if (qn >= 64) {
+                const S fresh = load(queue[lane]);
+                const int rest = qn - 64;
+                const int moved = lane < rest ? queue[64 + lane] : 0;
+                wave_sync();
+                if (lane < rest) queue[lane] = moved;
+                wave_sync();
+                qn = rest;
+                if (have) run(pend, true);
+                pend = fresh;
+                have = true;
+            }
+        }
+        gi = gn;
+        cur = nxt;
+    }
+    const bool tail = lane < qn;
+    S last{};
+    if (tail) last = load(queue[lane]);
+    if (have) run(pend, true);
+    if (qn > 0) run(last, tail);
 }
 
 }  // namespace h4d

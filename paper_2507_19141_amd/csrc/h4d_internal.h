@@ -55,11 +55,17 @@ struct TileMap {
     // (hashed, T a power of two of at least one tile, pi_1 = 1 and 2 N_s <= tile
     // rows: the pair's hashes differ only in bits below log2(2 N_s)).
     uint32_t pair_cotiled;
+    // Bit l set: the mask pass also stores, per (query, level), the tile of each of
+    // the eight x-pairs (one byte each), and the scatter visits a query's pairs in
+    // its tile from those bytes.  Levels with pair_cotiled and at most 256 tiles,
+    // when make_tile_map is asked for them.
+    uint32_t pair_words;
 };
-TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes);
+TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes, bool pair_words = false);
 // Workspace of the scatter: one 32-bit tile mask per (query, level), level-major
 // with the query count padded to a multiple of four so that every level starts on
-// a 16-byte boundary (the scan reads four masks per load).
+// a 16-byte boundary (the scan reads four masks per load); then the per-pair tile
+// bytes, 8 bytes per (query, level), in the same order.
 constexpr int64_t mask_stride(int64_t n) { return (n + 3) & ~(int64_t)3; }
 size_t scatter_mask_bytes(int n, int L);
 // A second feature gradient for the pair form (eps set): added, times scale, at x's
