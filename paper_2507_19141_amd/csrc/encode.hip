@@ -186,7 +186,6 @@ __device__ __forceinline__ void scatter_pair_words(const DevGrid& g, const TileM
                                                    const G* __restrict__ src, int64_t lstride, int64_t qstride,
                                                    G scale, int* queue, int2* overflow, G* tile) {
     const int lane = threadIdx.x & 63;
-    const uint64_t below = (1ull << lane) - 1ull;
     int2* ovf = overflow + (threadIdx.x >> 6) * kOverflowCap;
     const uint32_t rmask = (1u << tm.tile_shift[l]) - 1u;
     const G* gl = src + (int64_t)l * lstride;
@@ -195,7 +194,7 @@ __device__ __forceinline__ void scatter_pair_words(const DevGrid& g, const TileM
     auto visit = [&](float4 x, const G (&gv)[F], uint32_t pm, int q) {
         const uint32_t rest = pm & (pm - 1u);
         const uint64_t bal = __ballot(rest != 0u);
-        if (rest) ovf[ovn + __popcll(bal & below)] = make_int2(q, (int)rest);
+        if (rest) ovf[ovn + lane_rank(bal)] = make_int2(q, (int)rest);
         ovn += (int)__popcll(bal);
         wave_sync();
         if (pm) pair_contrib<G, F>(g, l, x, __builtin_ctz(pm), gv, rmask, tile);
@@ -258,9 +257,16 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
     __shared__ int queue[kQueueCap];
     __shared__ int2 overflow[PAIR ? 1 : kScatterBlock / 64 * kOverflowCap];
     G* tile = reinterpret_cast<G*>(smem);
+    // XCD placement: XCD x works on the contiguous run [x per, (x + 1) per) of the
+    // level-ordered tile list, so its L2 holds the masks, pair bytes and gradients of
+    // two or three levels instead of every XCD fetching every level's.
+    const int tiles = tm.tile_start[g.L];
+    const int per = xcd_items_per(tiles);
+    const int tix = ((int)blockIdx.x % kXcds) * per + (int)blockIdx.x / kXcds;
+    if ((int)blockIdx.x / kXcds >= per || tix >= tiles) return;
     int l = 0;
-    while (l + 1 < g.L && (int)blockIdx.x >= tm.tile_start[l + 1]) ++l;
-    const uint32_t t_in_level = (uint32_t)((int)blockIdx.x - tm.tile_start[l]);
+    while (l + 1 < g.L && tix >= tm.tile_start[l + 1]) ++l;
+    const uint32_t t_in_level = (uint32_t)(tix - tm.tile_start[l]);
     const uint32_t first = t_in_level << tm.tile_shift[l];
     const uint32_t base = g.off[l] + first;
     const uint32_t cnt = min(1u << tm.tile_shift[l], (uint32_t)tm.level_rows[l] - first);
@@ -382,7 +388,7 @@ static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt
     const size_t lds = (size_t)tm.max_rows * F * sizeof(G);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(tm.tile_start[g.L]), dim3(kScatterBlock), lds, s, g, tm,
+    hipLaunchKernelGGL(kern, dim3((unsigned)(kXcds * xcd_items_per(tm.tile_start[g.L]))), dim3(kScatterBlock), lds, s, g, tm,
                        reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n, mask, words,
                        static_cast<const G*>(src), ls, qs, (G)scale, static_cast<G*>(d_table), overwrite ? 1 : 0,
                        MainGrad<G>{static_cast<const G*>(main.src), main.lstride, main.qstride, (G)main.scale});

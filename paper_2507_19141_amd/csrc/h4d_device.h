@@ -27,10 +27,16 @@ __device__ __forceinline__ bool xcd_item(int items, int chunks, int& level, int&
     return true;
 }
 
-// Clamp to [0, 1]; NaN fails both comparisons and becomes 0.
+// Clamp to [0, 1], NaN to 0: the median of (x, 0, 1).  The hardware median returns
+// the smaller of the other two inputs when one input is a NaN, so a NaN gives 0; the
+// canonicalization first turns a signaling NaN into a quiet one.
 __device__ __forceinline__ float clamp_unit(float x) {
-    x = (x >= 0.0f) ? x : 0.0f;
-    return (x <= 1.0f) ? x : 1.0f;
+    return __builtin_amdgcn_fmed3f(__builtin_canonicalizef(x), 0.0f, 1.0f);
+}
+
+// Rank of this lane among the lanes set in a ballot below it (lanes 0 .. lane - 1).
+__device__ __forceinline__ int lane_rank(uint64_t bal) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
 }
 
 // Lower vertex and fractional offset along one dimension: pos = x * N rounded once
@@ -246,37 +252,65 @@ __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAd
 
 // Add v to an FP32 word of LDS.  gfx950 runs ds_add_f32 at about one active lane
 // per three clocks per CU, while its integer LDS atomics run near full rate, so the
-// add is a compare-and-swap loop on the bit pattern: read, add in FP32, swap in if
-// the word is unchanged, else retry with the value the swap returned.  Each add
-// still rounds once; the order of the adds is unspecified, as with any atomic.
+// add is a compare-and-swap on the bit pattern: read, add in FP32, swap in if the
+// word is unchanged, else try again from the value the swap returned.  A lane still
+// failing after kCasTries swaps (heavy contention: many queries in one cell, as when
+// every query has the same timestamp) falls back to ds_add_f32, whose hardware
+// serialises same-word adds, instead of going round once per contending lane.  Each
+// add rounds once either way; the order of the adds is unspecified, as with any
+// atomic.
+constexpr int kCasTries = 3;
+
 __device__ __forceinline__ void lds_add(float* p, float v) {
     unsigned int* u = reinterpret_cast<unsigned int*>(p);
-    // A plain load: a stale value only costs one more round of the loop (a volatile
-    // load would become a flat access that waits for every outstanding global load).
+    // A plain load: a stale value only costs one more swap (a volatile load would
+    // become a flat access that waits for every outstanding global load).
     unsigned int seen = *u;
-    while (true) {
-        const unsigned int want = __float_as_uint(__uint_as_float(seen) + v);
-        const unsigned int prev = atomicCAS(u, seen, want);
-        if (prev == seen) break;
+    for (int k = 0; k < kCasTries; ++k) {
+        const unsigned int prev = atomicCAS(u, seen, __float_as_uint(__uint_as_float(seen) + v));
+        if (prev == seen) return;
         seen = prev;
     }
+    atomicAdd(p, v);
 }
 __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
 
-// Add (v0, v1) to two adjacent FP32 words of LDS (8-byte aligned) with one 64-bit
-// compare-and-swap loop.
-__device__ __forceinline__ void lds_add2(float* p, float v0, float v1) {
+__device__ __forceinline__ unsigned long long add_pair_bits(unsigned long long seen, float v0, float v1) {
+    return (unsigned long long)__float_as_uint(__uint_as_float((unsigned int)seen) + v0) |
+           ((unsigned long long)__float_as_uint(__uint_as_float((unsigned int)(seen >> 32)) + v1) << 32);
+}
+
+// Further swaps after a failed first one, then the ds_add_f32 fallback (lds_add).
+__device__ __forceinline__ void lds_add2_retry(float* p, float v0, float v1, unsigned long long seen) {
     unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
-    unsigned long long seen = *u;
-    while (true) {
-        const float a = __uint_as_float((unsigned int)seen) + v0;
-        const float b = __uint_as_float((unsigned int)(seen >> 32)) + v1;
-        const unsigned long long want =
-            (unsigned long long)__float_as_uint(a) | ((unsigned long long)__float_as_uint(b) << 32);
-        const unsigned long long prev = atomicCAS(u, seen, want);
-        if (prev == seen) break;
+    for (int k = 1; k < kCasTries; ++k) {
+        const unsigned long long prev = atomicCAS(u, seen, add_pair_bits(seen, v0, v1));
+        if (prev == seen) return;
         seen = prev;
     }
+    atomicAdd(p, v0);
+    atomicAdd(p + 1, v1);
+}
+
+// Add (v0, v1) to two adjacent FP32 words of LDS (8-byte aligned) with 64-bit
+// compare-and-swaps, as lds_add does for one word.
+__device__ __forceinline__ void lds_add2(float* p, float v0, float v1) {
+    unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
+    const unsigned long long seen = *u;
+    const unsigned long long prev = atomicCAS(u, seen, add_pair_bits(seen, v0, v1));
+    if (prev != seen) lds_add2_retry(p, v0, v1, prev);
+}
+
+// Add (a0, a1) at p and (b0, b1) at q (8-byte aligned FP32 pairs in LDS, p != q) as
+// lds_add2 does, with both reads and both first swaps in flight together.
+__device__ __forceinline__ void lds_add2_two(float* p, float a0, float a1, float* q, float b0, float b1) {
+    unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
+    unsigned long long* v = reinterpret_cast<unsigned long long*>(q);
+    const unsigned long long su = *u, sv = *v;
+    const unsigned long long ru = atomicCAS(u, su, add_pair_bits(su, a0, a1));
+    const unsigned long long rv = atomicCAS(v, sv, add_pair_bits(sv, b0, b1));
+    if (ru != su) lds_add2_retry(p, a0, a1, ru);
+    if (rv != sv) lds_add2_retry(q, b0, b1, rv);
 }
 
 // Add F values to one tile row.
@@ -433,8 +467,13 @@ __device__ __forceinline__ void pair_contrib(const DevGrid& g, int l, float4 x, 
     const G wz = dz ? G(c.fz) : G(1) - G(c.fz);
     const G wt = dt ? G(c.ft) : G(1) - G(c.ft);
     const G w = (wy * wz) * wt;
-    lds_add_row<G, F>(tile + r0 * F, gv, (G(1) - G(c.fx)) * w);
-    lds_add_row<G, F>(tile + r1 * F, gv, G(c.fx) * w);
+    const G w0 = (G(1) - G(c.fx)) * w, w1 = G(c.fx) * w;
+    if constexpr (sizeof(G) == 4 && F == 2) {
+        lds_add2_two(tile + r0 * 2, w0 * gv[0], w0 * gv[1], tile + r1 * 2, w1 * gv[0], w1 * gv[1]);
+    } else {
+        lds_add_row<G, F>(tile + r0 * F, gv, w0);
+        lds_add_row<G, F>(tile + r1 * F, gv, w1);
+    }
 }
 
 // Orders one wavefront's LDS queue writes before its reads by other lanes.
@@ -504,50 +543,57 @@ __device__ __forceinline__ void masked_queue_loop(int n, const uint32_t* __restr
 
 // As masked_queue_loop, but run(s, active) is always called by the whole wavefront
 // (active is false for the lanes of a partial last batch), so that run may use
-// wavefront-wide operations.
+// wavefront-wide operations.  Each step loads kScanLoads 16-byte groups of masks per
+// lane (1024 queries per wavefront) with their loads issued together, so a step waits
+// for its masks once; the batch loads issued while scanning are then waited for only
+// by the run of that batch, one batch later.
+constexpr int kScanLoads = 4;
 template <int BLOCK, typename Load, typename Run>
 __device__ __forceinline__ void masked_queue_loop_wave(int n, const uint32_t* __restrict__ lmask, uint32_t bit,
                                                        int* wqueue, Load load, Run run) {
     static_assert(BLOCK % 64 == 0, "whole wavefronts");
     using S = decltype(load(0));
+    constexpr int kWaves = BLOCK / 64;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     int* queue = wqueue + wave * 128;
     const uint4* __restrict__ m4 = reinterpret_cast<const uint4*>(lmask);
     const int groups = (n + 3) >> 2;
-    const uint64_t below = (1ull << lane) - 1ull;
     int qn = 0;
-    bool have = false;
+    bool have = false;  // a loaded batch waits in `pend` (wave-uniform)
     S pend{};
-    int gi = wave * 64 + lane;
-    uint4 cur = gi < groups ? m4[gi] : make_uint4(0u, 0u, 0u, 0u);
-    for (int g0 = wave * 64; g0 < groups; g0 += BLOCK) {
-        const int gn = gi + BLOCK;
-        const uint4 nxt = gn < groups ? m4[gn] : make_uint4(0u, 0u, 0u, 0u);
-        const uint32_t mm[4] = {cur.x, cur.y, cur.z, cur.w};
+    for (int g0 = wave * 64 * kScanLoads; g0 < groups; g0 += kWaves * 64 * kScanLoads) {
+        uint4 m[kScanLoads];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int q = 4 * gi + j;
-            const bool hit = (mm[j] & bit) != 0u && q < n;
-            const uint64_t bal = __ballot(hit);
-            if (hit) queue[qn + __popcll(bal & below)] = q;
-            qn += (int)__popcll(bal);
-            wave_sync();
-            if (qn >= 64) {
-                const S fresh = load(queue[lane]);
-                const int rest = qn - 64;
-                const int moved = lane < rest ? queue[64 + lane] : 0;
+        for (int k = 0; k < kScanLoads; ++k) {
+            const int gi = g0 + k * 64 + lane;
+            m[k] = gi < groups ? m4[gi] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < kScanLoads; ++k) {
+            const uint32_t mm[4] = {m[k].x, m[k].y, m[k].z, m[k].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int q = 4 * (g0 + k * 64 + lane) + j;
+                const bool hit = (mm[j] & bit) != 0u && q < n;
+                const uint64_t bal = __ballot(hit);
+                if (hit) queue[qn + lane_rank(bal)] = q;
+                qn += (int)__popcll(bal);
                 wave_sync();
-                if (lane < rest) queue[lane] = moved;
-                wave_sync();
-                qn = rest;
-                if (have) run(pend, true);
-                pend = fresh;
-                have = true;
+                if (qn >= 64) {
+                    const S fresh = load(queue[lane]);
+                    const int rest = qn - 64;
+                    const int moved = lane < rest ? queue[64 + lane] : 0;
+                    wave_sync();
+                    if (lane < rest) queue[lane] = moved;
+                    wave_sync();
+                    qn = rest;
+                    if (have) run(pend, true);
+                    pend = fresh;
+                    have = true;
+                }
             }
         }
-        gi = gn;
-        cur = nxt;
     }
     const bool tail = lane < qn;
     S last{};
