@@ -138,10 +138,13 @@ h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* tabl
  *           in layout, which writes every row, zeros where no corner lands)
  * Owner-computes scatter: one workgroup per (level, tile of consecutive table rows)
  * sums its rows' updates in LDS and adds them to d_table; no device-wide atomics.
- * A pre-pass writes a per-(query, level) mask of touched tiles into `workspace`
- * (device, at least hash4d_encode_backward_workspace_bytes) so that each tile only
- * works on the queries that reach it.  The LDS adds (compare-and-swap, one FP32
- * rounding each) make the summation order, hence the last bits, vary run to run. */
+ * A pre-pass writes a per-(query, level) mask of touched tiles (and, on hashed
+ * levels, each x-pair's tile) into `workspace` (device, 16-byte aligned, at least
+ * hash4d_encode_backward_workspace_bytes) so that each tile only works on the
+ * queries that reach it; it also counts the queries per tile of the dense levels,
+ * and a tile that many queries reach is split over several workgroups whose partial
+ * tiles the workspace holds.  The LDS adds (one FP32 rounding each) make the
+ * summation order, hence the last bits, vary run to run. */
 size_t hash4d_encode_backward_workspace_bytes(const h4d_grid* g, int64_t n);
 h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
                                   h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,

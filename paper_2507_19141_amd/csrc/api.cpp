@@ -125,12 +125,19 @@ static h4d_status check_mlp(const h4d_mlp* m, h4d_dtype dt) {
     return check_dtype(dt);
 }
 
+// Workspace of the tiled scatter for grid g and n queries.
+static size_t scatter_ws(const h4d_grid* g, int64_t n) {
+    int64_t rows[H4D_MAX_LEVELS];
+    rows_of(*g, rows);
+    return scatter_ws_bytes(to_device(*g), rows, (int)n);
+}
+
 // Deformation backward workspace: [decoder partials | d_feat [L, n, F] | tile masks].
 static size_t deform_ws(const h4d_grid* g, const h4d_mlp* m, h4d_dtype dt, int64_t n) {
     const size_t el = dt == H4D_F64 ? sizeof(double) : sizeof(float);
     const size_t a = (mlp_workspace_bytes(dt, m->in, m->out, (int)n) + 255) / 256 * 256;
     const size_t b = ((size_t)n * g->L * g->F * el + 255) / 256 * 256;
-    return a + b + scatter_mask_bytes((int)n, g->L);
+    return a + b + scatter_ws(g, n);
 }
 
 h4d_status validate_grid(const h4d_grid* g) { return check_grid(g); }
@@ -250,7 +257,7 @@ h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* tabl
 
 size_t hash4d_encode_backward_workspace_bytes(const h4d_grid* g, int64_t n) {
     if (check_grid(g) != H4D_OK || n < 0 || n > kMaxQ || n * (int64_t)g->L > kMaxN) return 0;
-    return scatter_mask_bytes((int)n, g->L);
+    return scatter_ws(g, n);
 }
 
 // Validation and launch shared by hash4d_encode_backward and its static-workspace
@@ -275,7 +282,7 @@ static h4d_status encode_backward_call(const h4d_grid* g, h4d_dtype grad_dt, con
         return hip_status(launch_zero_words(d_table, words, (hipStream_t)stream), where);
     }
     if (!d_feat || !d_table) return fail(H4D_EINVAL, "d_feat or d_table is NULL");
-    const size_t need = scatter_mask_bytes((int)n, g->L);
+    const size_t need = scatter_ws(g, n);
     if (static_ws) {
         if (need > kStaticScratchBytes)
             return fail(H4D_EINVAL, "n=%lld, L=%d need %zu bytes of workspace; the static workspace holds %zu",
@@ -357,7 +364,7 @@ h4d_status hash4d_corner_indices(const h4d_grid* g, const float* xyzt, int64_t n
 // Smoothness workspace: [d = G(x) - G(x + eps), level-major | tile masks].
 static size_t smooth_ws(const h4d_grid* g, h4d_dtype table_dt, int64_t n) {
     const size_t d = ((size_t)n * g->L * g->F * (table_dt == H4D_F64 ? sizeof(double) : sizeof(float)) + 255) / 256 * 256;
-    return d + scatter_mask_bytes((int)n, g->L);
+    return d + scatter_ws(g, n);
 }
 
 size_t smoothness_workspace_bytes(const h4d_grid* g, h4d_dtype table_dt, int64_t n) {

@@ -6,6 +6,8 @@
 // instead of every XCD streaming the whole table through its L2.
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <mutex>
 
 #include "h4d_device.h"
@@ -69,23 +71,34 @@ __global__ __launch_bounds__(kEncodeBlock) void k_encode(DevGrid g, const TT* __
 // PAIR: each query also subtracts the same gradient at the corners of x + eps (the
 // second term of Eq. 11).
 
+// Load balance of the dense levels.  A dense level's tiles hold fixed runs of
+// vertices, so when the queries crowd into a few cells (every query at one timestamp,
+// a clustered cloud) a few of its tiles receive most of the level's updates and the
+// scatter waits for them.  The mask pass therefore also counts, per dense level, the
+// queries that touch each tile bit in each chunk of kMaskChunk queries; a one-workgroup
+// plan (k_tile_plan) splits a heavy tile's queries into up to kMaxSplits ranges, each
+// worked by its own workgroup on its own copy of the tile in LDS and written to the
+// workspace as a partial tile; a last kernel (k_tile_combine) adds each split tile's
+// partials in range order and writes its rows.  Hashed levels spread their rows by the
+// hash and are not split.
+constexpr int kMaskChunk = 1024;            // queries per counting workgroup of the mask pass
+constexpr int kMaxSplits = 16;
+constexpr int kPlanTiles = 4096;            // tiles the plan may split (the first ones)
+constexpr int kMaxExtraRanges = 96;         // extra workgroups for split tiles, at most
+
+// Tile mask (and pair tile bytes) of one (query, level), and the query's position.
 template <bool PAIR>
-__global__ __launch_bounds__(kEncodeBlock) void k_tile_mask(DevGrid g, TileMap tm, const float4* __restrict__ xyzt,
-                                                            const float4* __restrict__ eps, int n,
-                                                            uint32_t* __restrict__ mask, uint2* __restrict__ words) {
-    const int l = blockIdx.y;
-    const int q = blockIdx.x * kEncodeBlock + threadIdx.x;
-    if (q >= n) return;
-    const float4 x = xyzt[q];
+__device__ __forceinline__ uint32_t query_tile_mask(const DevGrid& g, const TileMap& tm, int l, float4 x,
+                                                    const float4* __restrict__ eps, int q, int n,
+                                                    uint2* __restrict__ words) {
     if (!PAIR && ((tm.pair_words >> l) & 1u)) {
         const uint2 b = pair_tile_bytes(g, tm, l, level_cell(g, l, x));
         const int bs = tm.bit_shift[l];
-        uint32_t m = 0;
+        uint32_t m = 0u;
 #pragma unroll
         for (int k = 0; k < 32; k += 8) m |= (1u << (((b.x >> k) & 0xffu) >> bs)) | (1u << (((b.y >> k) & 0xffu) >> bs));
-        mask[(int64_t)l * mask_stride(n) + q] = m;
         words[(int64_t)l * mask_stride(n) + q] = b;
-        return;
+        return m;
     }
     uint32_t m = corner_tile_mask(g, tm, l, x);
     if constexpr (PAIR) {
@@ -94,7 +107,204 @@ __global__ __launch_bounds__(kEncodeBlock) void k_tile_mask(DevGrid g, TileMap t
                                       __fadd_rn(x.w, e.w));
         m |= corner_tile_mask(g, tm, l, xp);
     }
-    mask[(int64_t)l * mask_stride(n) + q] = m;
+    return m;
+}
+
+// Grid (ceil(n / kEncodeBlock), L).  Hashed levels: one query per thread.  Dense
+// levels: the first ceil(n / kMaskChunk) workgroups take kMaskChunk queries each and
+// also count, per tile bit, the queries that touch it (counts[l][chunk][32]).
+template <bool PAIR>
+__global__ __launch_bounds__(kEncodeBlock) void k_tile_mask(DevGrid g, TileMap tm, const float4* __restrict__ xyzt,
+                                                            const float4* __restrict__ eps, int n,
+                                                            uint32_t* __restrict__ mask, uint2* __restrict__ words,
+                                                            uint32_t* __restrict__ counts, int nchunks) {
+    const int l = blockIdx.y;
+    if (!((g.dense_bits >> l) & 1u)) {
+        const int q = blockIdx.x * kEncodeBlock + threadIdx.x;
+        if (q >= n) return;
+        mask[(int64_t)l * mask_stride(n) + q] = query_tile_mask<PAIR>(g, tm, l, xyzt[q], eps, q, n, words);
+        return;
+    }
+    const int chunk = blockIdx.x;
+    if (chunk >= nchunks) return;  // workgroup-uniform
+    __shared__ uint32_t cnt[32];
+    if (threadIdx.x < 32) cnt[threadIdx.x] = 0u;
+    constexpr int kPerThread = kMaskChunk / kEncodeBlock;
+    float4 xs[kPerThread];  // every load in flight before the first use
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) {
+        const int q = chunk * kMaskChunk + i * kEncodeBlock + (int)threadIdx.x;
+        xs[i] = q < n ? xyzt[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) {
+        const int q = chunk * kMaskChunk + i * kEncodeBlock + (int)threadIdx.x;
+        if (q >= n) continue;
+        uint32_t m = query_tile_mask<PAIR>(g, tm, l, xs[i], eps, q, n, words);
+        mask[(int64_t)l * mask_stride(n) + q] = m;
+        while (m) {  // a dense level's corners touch a few neighbouring tiles
+            atomicAdd(&cnt[__builtin_ctz(m)], 1u);
+            m &= m - 1u;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) counts[((int64_t)l * nchunks + chunk) * 32 + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// The plan.  Entry t < tiles is tile t's first (or only) query range; entries tiles
+// .. tiles + extras - 1 are the other ranges of the split tiles.  An entry holds the
+// tile, its range, how many ranges the tile is split into, and the tile's first
+// partial-tile slot.  info = {extras, split tiles}; split[i] = the i-th split tile.
+// A dense tile's cost is its query count times kDenseCost (a dense visit adds about
+// four x-pairs to the tile, a hashed visit about one).  With h the expected query
+// count of a hashed tile (8 pairs over P tiles), a tile costing at most 2 h stays
+// whole (more workgroups would add a round and save little); a costlier one is split
+// into ceil(cost / target) ranges, at most kMaxSplits, with target = 5/4 h raised
+// until the extra ranges fit in `extra`.
+constexpr int kDenseCost = 3;
+
+__global__ __launch_bounds__(1024) void k_tile_plan(DevGrid g, TileMap tm, const uint32_t* __restrict__ counts,
+                                                    int nchunks, float target0, int extra, int4* __restrict__ plan,
+                                                    int* __restrict__ info, int* __restrict__ split) {
+    __shared__ uint32_t cost[kPlanTiles];
+    __shared__ uint32_t ksum[1024];
+    __shared__ uint32_t ssum[1024];
+    __shared__ float target_s;
+    const int tiles = tm.tile_start[g.L];
+    const int cand = min(tiles, kPlanTiles);
+    for (int t = threadIdx.x; t < cand; t += blockDim.x) cost[t] = 0u;
+    __syncthreads();
+    // queries per dense tile from the (tile bit, chunk) counts of the dense levels.
+    // Item i = (the (i / 32)-th dense level, bit i % 32); wavefront w sums items w,
+    // w + nwaves, ... four at a time, each lane loading chunks lane, lane + 64, ... of
+    // all four before adding any, then a butterfly; so no two lanes add into one word.
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
+    const float whole = target0 * (2.f / 1.25f);
+    if (threadIdx.x == 0) target_s = target0;
+    const int ndense = __popc(g.dense_bits & (g.L >= 32 ? 0xffffffffu : ((1u << g.L) - 1u)));
+    for (int i0 = wave * 4; i0 < ndense * 32; i0 += nwaves * 4) {
+        int lv[4], bit[4];
+        bool ok[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = i0 + j, dl = i / 32;
+            bit[j] = i % 32;
+            int l = 0, seen = -1;
+            for (; l < g.L; ++l)
+                if (((g.dense_bits >> l) & 1u) && ++seen == dl) break;
+            lv[j] = l;
+            ok[j] = i < ndense * 32 && l < g.L && tm.tile_start[l] < cand &&
+                    (bit[j] << tm.bit_shift[l]) < tm.tile_start[l + 1] - tm.tile_start[l];
+        }
+        uint32_t sum[4] = {0u, 0u, 0u, 0u};
+        for (int k0 = 0; k0 < nchunks; k0 += 4 * 64) {
+            uint32_t v[4][4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int k = k0 + c * 64 + lane;
+                    v[j][c] = ok[j] && k < nchunks ? counts[((int64_t)lv[j] * nchunks + k) * 32 + bit[j]] : 0u;
+                }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) sum[j] += (v[j][0] + v[j][1]) + (v[j][2] + v[j][3]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) sum[j] += __shfl_xor(sum[j], d);
+            if (!ok[j]) continue;
+            // every tile of the bit gets its share of the bit's count, times the dense
+            // weight; a tile up to twice a hashed tile's expected work stays whole (0)
+            const int l = lv[j];
+            const float c = (float)(sum[j] >> tm.bit_shift[l]) * kDenseCost;
+            const uint32_t cv = c <= whole ? 0u : (uint32_t)fminf(c, 4.0e9f);
+            const int t0 = tm.tile_start[l] + (bit[j] << tm.bit_shift[l]);
+            const int t1 = min(min(tm.tile_start[l + 1], cand), t0 + (1 << tm.bit_shift[l]));
+            for (int t = t0 + lane; t < t1; t += 64) cost[t] = cv;
+        }
+    }
+    __syncthreads();
+    for (int round = 0; round < 24; ++round) {  // raise the target until the extra ranges fit
+        const float target = target_s;
+        uint32_t mysum = 0u;
+        for (int t = threadIdx.x; t < cand; t += blockDim.x)
+            mysum += min((uint32_t)kMaxSplits, max(1u, (uint32_t)ceilf((float)cost[t] / target))) - 1u;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) mysum += __shfl_xor(mysum, d);
+        if (lane == 0) ksum[wave] = mysum;
+        __syncthreads();
+        uint32_t all = 0u;
+        for (int w = 0; w < nwaves; ++w) all += ksum[w];
+        const bool fits = all <= (uint32_t)extra;
+        __syncthreads();
+        if (fits) break;
+        if (threadIdx.x == 0) target_s = target * 1.5f;
+        __syncthreads();
+    }
+    const float target = target_s;
+    // exclusive positions over the candidate tiles (four per thread): extra ranges
+    // (k - 1) and split tiles (1 if split)
+    constexpr int kPer = kPlanTiles / 1024;
+    uint32_t kk[kPer], lext = 0u, lsplit = 0u;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int t = threadIdx.x * kPer + j;
+        uint32_t k = 1u;
+        if (t < cand) k = min((uint32_t)kMaxSplits, max(1u, (uint32_t)ceilf((float)cost[t] / target)));
+        kk[j] = k;
+        lext += k - 1u;
+        lsplit += k > 1u ? 1u : 0u;
+    }
+    // inclusive scans within the wavefront, then the wavefront totals
+    uint32_t iext = lext, isplit = lsplit;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t a = __shfl_up(iext, d), b = __shfl_up(isplit, d);
+        if (lane >= d) {
+            iext += a;
+            isplit += b;
+        }
+    }
+    if (lane == 63) {
+        ksum[wave] = iext;
+        ssum[wave] = isplit;
+    }
+    __syncthreads();
+    uint32_t before_e = 0u, before_s = 0u, total_e = 0u, total_s = 0u;
+    for (int w = 0; w < nwaves; ++w) {
+        if (w < wave) {
+            before_e += ksum[w];
+            before_s += ssum[w];
+        }
+        total_e += ksum[w];
+        total_s += ssum[w];
+    }
+    const bool fits = total_e <= (uint32_t)extra;
+    uint32_t ext = before_e + iext - lext;   // extra ranges before this thread's tiles
+    uint32_t sp = before_s + isplit - lsplit;  // split tiles before them
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int t = threadIdx.x * kPer + j;
+        if (t >= cand) break;
+        const int k = fits ? (int)kk[j] : 1;
+        // a split tile's K partial slots start at (split tiles before it) + (extra
+        // ranges before it): K slots per split tile, in tile order
+        const int slot = (int)(sp + ext);
+        plan[t] = make_int4(t, 0, k, k > 1 ? slot : -1);
+        for (int r = 1; r < k; ++r) plan[tiles + (int)ext + r - 1] = make_int4(t, r, k, slot);
+        if (k > 1) {
+            split[sp] = t;
+            ext += (uint32_t)k - 1u;
+            sp += 1u;
+        }
+    }
+    for (int t = cand + (int)threadIdx.x; t < tiles; t += blockDim.x) plan[t] = make_int4(t, 0, 1, -1);
+    if (threadIdx.x == 0) {
+        info[0] = fits ? (int)total_e : 0;
+        info[1] = fits ? (int)total_s : 0;
+    }
 }
 
 // 1024 threads share each tile: the 128 KiB of LDS allows one workgroup per CU, and
@@ -179,9 +389,10 @@ struct WordQuery {
 
 constexpr int kOverflowCap = 128;  // entries per wavefront
 
+// Queries [q0, q0 + n) of the level; lmask and lwords point at query q0's entries.
 template <typename G, int F>
 __device__ __forceinline__ void scatter_pair_words(const DevGrid& g, const TileMap& tm, int l, uint32_t tau,
-                                                   uint32_t bit, const float4* __restrict__ xyzt, int n,
+                                                   uint32_t bit, const float4* __restrict__ xyzt, int q0, int n,
                                                    const uint32_t* __restrict__ lmask, const uint2* __restrict__ lwords,
                                                    const G* __restrict__ src, int64_t lstride, int64_t qstride,
                                                    G scale, int* queue, int2* overflow, G* tile) {
@@ -225,13 +436,14 @@ __device__ __forceinline__ void scatter_pair_words(const DevGrid& g, const TileM
     };
     masked_queue_loop_wave<kScatterBlock>(
         n, lmask, bit, queue,
-        [&](int q) {
+        [&](int i) {
             WordQuery<G, F> t;
+            const int q = q0 + i;
             const G* gp = gl + (int64_t)q * qstride;
 #pragma unroll
             for (int f = 0; f < F; ++f) t.gv[f] = gp[f];
             t.x = xyzt[q];
-            t.wd = lwords[q];
+            t.wd = lwords[i];
             t.q = q;
             return t;
         },
@@ -250,6 +462,9 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
                                                                 const float4* __restrict__ eps, int n,
                                                                 const uint32_t* __restrict__ mask,
                                                                 const uint2* __restrict__ words,
+                                                                const int4* __restrict__ plan,
+                                                                const int* __restrict__ plan_info,
+                                                                G* __restrict__ partials, int slot_elems,
                                                                 const G* __restrict__ src, int64_t lstride,
                                                                 int64_t qstride, G scale, G* __restrict__ d_table,
                                                                 int overwrite, MainGrad<G> mg) {
@@ -258,12 +473,23 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
     __shared__ int2 overflow[PAIR ? 1 : kScatterBlock / 64 * kOverflowCap];
     G* tile = reinterpret_cast<G*>(smem);
     // XCD placement: XCD x works on the contiguous run [x per, (x + 1) per) of the
-    // level-ordered tile list, so its L2 holds the masks, pair bytes and gradients of
-    // two or three levels instead of every XCD fetching every level's.
+    // level-ordered tiles, so its L2 holds the masks, pair bytes and gradients of two or
+    // three levels instead of every XCD fetching every level's; the extra ranges of split
+    // tiles go round-robin to the XCDs, since they are the heavy ones.
     const int tiles = tm.tile_start[g.L];
     const int per = xcd_items_per(tiles);
-    const int tix = ((int)blockIdx.x % kXcds) * per + (int)blockIdx.x / kXcds;
-    if ((int)blockIdx.x / kXcds >= per || tix >= tiles) return;
+    const int x = (int)blockIdx.x % kXcds, sx = (int)blockIdx.x / kXcds;
+    int six;
+    if (sx < per) {
+        six = x * per + sx;
+        if (six >= tiles) return;
+    } else {  // the extra ranges, round-robin over the XCDs
+        six = (sx - per) * kXcds + x;
+        if (six >= plan_info[0]) return;
+        six += tiles;
+    }
+    const int4 pe = plan[six];
+    const int tix = pe.x, range = pe.y, nranges = pe.z;
     int l = 0;
     while (l + 1 < g.L && tix >= tm.tile_start[l + 1]) ++l;
     const uint32_t t_in_level = (uint32_t)(tix - tm.tile_start[l]);
@@ -271,19 +497,28 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
     const uint32_t base = g.off[l] + first;
     const uint32_t cnt = min(1u << tm.tile_shift[l], (uint32_t)tm.level_rows[l] - first);
     const uint32_t bit = tile_bit(tm, l, first);
+    // this workgroup's queries: range r of nranges, boundaries on multiples of four
+    const int q0 = (int)(((int64_t)n * range / nranges) & ~(int64_t)3);
+    const int q1 = range + 1 == nranges ? n : (int)(((int64_t)n * (range + 1) / nranges) & ~(int64_t)3);
     for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) tile[i] = G(0);
     __syncthreads();
+    const uint32_t* lmask = mask + (int64_t)l * mask_stride(n) + q0;
     if (!PAIR && ((tm.pair_words >> l) & 1u)) {
-        scatter_pair_words<G, F>(g, tm, l, t_in_level, bit, xyzt, n, mask + (int64_t)l * mask_stride(n),
-                                 words + (int64_t)l * mask_stride(n), src, lstride, qstride, scale, queue, overflow,
-                                 tile);
+        scatter_pair_words<G, F>(g, tm, l, t_in_level, bit, xyzt, q0, q1 - q0, lmask,
+                                 words + (int64_t)l * mask_stride(n) + q0, src, lstride, qstride, scale, queue,
+                                 overflow, tile);
     } else {
         masked_queue_loop<kScatterBlock>(
-            n, mask + (int64_t)l * mask_stride(n), bit, queue,
-            [&](int q) { return tile_load<G, F, PAIR>(l, xyzt, eps, src, lstride, qstride, mg, q); },
+            q1 - q0, lmask, bit, queue,
+            [&](int i) { return tile_load<G, F, PAIR>(l, xyzt, eps, src, lstride, qstride, mg, q0 + i); },
             [&](const TileQuery<G, F, PAIR>& t) { tile_run<G, F, PAIR>(g, tm, l, t, scale, mg, base, cnt, tile); });
     }
     __syncthreads();
+    if (nranges > 1) {  // a split tile: k_tile_combine adds the ranges' partial tiles
+        G* mine = partials + (int64_t)(pe.w + range) * slot_elems;
+        for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) mine[i] = tile[i];
+        return;
+    }
     // the tile's rows have no other owner: add them to d_table, or with overwrite set
     // write every row (the tiles of the levels cover all E rows)
     G* out = d_table + (size_t)base * F;
@@ -294,6 +529,33 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
             const G v = tile[i];
             if (v != G(0)) out[i] += v;
         }
+    }
+}
+
+// Rows of the split tiles: the sum of their ranges' partial tiles, in range order.
+// Workgroup (i, part) covers part `part` of kCombineParts of the i-th split tile.
+constexpr int kCombineParts = 4;
+template <typename G>
+__global__ __launch_bounds__(256) void k_tile_combine(DevGrid g, TileMap tm, const int4* __restrict__ plan,
+                                                      const int* __restrict__ plan_info,
+                                                      const int* __restrict__ split,
+                                                      const G* __restrict__ partials, int slot_elems,
+                                                      G* __restrict__ d_table, int overwrite) {
+    if ((int)blockIdx.x >= plan_info[1]) return;
+    const int tix = split[blockIdx.x];
+    const int4 pe = plan[tix];
+    int l = 0;
+    while (l + 1 < g.L && tix >= tm.tile_start[l + 1]) ++l;
+    const uint32_t first = (uint32_t)(tix - tm.tile_start[l]) << tm.tile_shift[l];
+    const uint32_t values = min(1u << tm.tile_shift[l], (uint32_t)tm.level_rows[l] - first) * (uint32_t)g.F;
+    const uint32_t chunk = (values + kCombineParts - 1) / kCombineParts;
+    const uint32_t lo = blockIdx.y * chunk, hi = min(values, lo + chunk);
+    G* out = d_table + (size_t)(g.off[l] + first) * g.F;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
+        G v = partials[(int64_t)pe.w * slot_elems + i];
+        for (int r = 1; r < pe.z; ++r) v += partials[(int64_t)(pe.w + r) * slot_elems + i];
+        if (overwrite) out[i] = v;
+        else if (v != G(0)) out[i] += v;
     }
 }
 
@@ -378,20 +640,78 @@ TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gb
     return tm;
 }
 
-size_t scatter_mask_bytes(int n, int L) { return (size_t)mask_stride(n) * L * (sizeof(uint32_t) + sizeof(uint2)); }
+// Workspace of the tiled scatter, each part 256-byte aligned: masks [L][stride] u32 |
+// pair tile bytes [L][stride] uint2 | per-chunk tile counts [L][chunks][32] u32 | plan
+// [tiles + extra] int4 | plan info (2 int) | split tiles [extra] int | partial tiles
+// [2 extra][slot].  One layout serves FP32 and FP64 gradients (the larger tile count
+// and tile of the two).
+struct ScatterWs {
+    size_t words, counts, plan, info, split, partials, total, slot_bytes;
+    int chunks, extra;
+};
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+static ScatterWs scatter_ws(const DevGrid& g, const int64_t* level_rows, int n) {
+    ScatterWs w;
+    int tiles = 0;
+    w.slot_bytes = 0;
+    for (int gbytes = 4; gbytes <= 8; gbytes += 4) {
+        const TileMap tm = make_tile_map(g, level_rows, g.F, gbytes);
+        tiles = max(tiles, tm.tile_start[g.L]);
+        for (int l = 0; l < g.L; ++l) {
+            const int64_t rows = min((int64_t)1 << tm.tile_shift[l], level_rows[l]);
+            w.slot_bytes = max(w.slot_bytes, (size_t)rows * g.F * gbytes);
+        }
+    }
+    w.chunks = (n + kMaskChunk - 1) / kMaskChunk;
+    w.extra = min(kMaxExtraRanges, max(8, tiles / 4));
+    const size_t masks = align256((size_t)mask_stride(n) * g.L * sizeof(uint32_t));
+    w.words = masks;
+    w.counts = w.words + align256((size_t)mask_stride(n) * g.L * sizeof(uint2));
+    w.plan = w.counts + align256((size_t)g.L * w.chunks * 32 * sizeof(uint32_t));
+    w.info = w.plan + align256((size_t)(tiles + w.extra) * sizeof(int4));
+    w.split = w.info + 256;
+    w.partials = w.split + align256((size_t)w.extra * sizeof(int));
+    w.total = w.partials + (size_t)2 * w.extra * w.slot_bytes;
+    return w;
+}
+
+size_t scatter_ws_bytes(const DevGrid& g, const int64_t* level_rows, int n) {
+    return scatter_ws(g, level_rows, n).total;
+}
+
+struct ScatterBufs {
+    uint32_t* mask;
+    uint2* words;
+    uint32_t* counts;
+    int4* plan;
+    int* info;
+    int* split;
+    void* partials;
+    int extra;
+    size_t slot_bytes;
+};
 
 template <typename G, int F, bool PAIR>
 static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt, const float* eps, int n,
-                          const uint32_t* mask, const uint2* words, const void* src, int64_t ls, int64_t qs,
-                          double scale, void* d_table, bool overwrite, const MainGradArg& main, hipStream_t s) {
+                          const ScatterBufs& b, const void* src, int64_t ls, int64_t qs, double scale, void* d_table,
+                          bool overwrite, const MainGradArg& main, hipStream_t s) {
     auto kern = k_scatter_tiled<G, F, PAIR>;
     const size_t lds = (size_t)tm.max_rows * F * sizeof(G);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(kXcds * xcd_items_per(tm.tile_start[g.L]))), dim3(kScatterBlock), lds, s, g, tm,
-                       reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n, mask, words,
-                       static_cast<const G*>(src), ls, qs, (G)scale, static_cast<G*>(d_table), overwrite ? 1 : 0,
+    const int rounds = xcd_items_per(tm.tile_start[g.L]) + xcd_items_per(b.extra);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(kXcds * rounds)), dim3(kScatterBlock), lds, s, g, tm,
+                       reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n, b.mask,
+                       b.words, b.plan, b.info, static_cast<G*>(b.partials),
+                       (int)(b.slot_bytes / sizeof(G)), static_cast<const G*>(src), ls, qs, (G)scale,
+                       static_cast<G*>(d_table), overwrite ? 1 : 0,
                        MainGrad<G>{static_cast<const G*>(main.src), main.lstride, main.qstride, (G)main.scale});
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tile_combine<G>, dim3((unsigned)b.extra, kCombineParts), dim3(256), 0, s, g, tm, b.plan,
+                       b.info, b.split, static_cast<const G*>(b.partials),
+                       (int)(b.slot_bytes / sizeof(G)), static_cast<G*>(d_table), overwrite ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -400,22 +720,38 @@ static hipError_t tiled_g(const DevGrid& g, const int64_t* level_rows, const flo
                           const void* src, int64_t ls, int64_t qs, double scale, void* d_table, void* mask_ws,
                           bool overwrite, const MainGradArg& main, hipStream_t s) {
     const TileMap tm = make_tile_map(g, level_rows, g.F, (int)sizeof(G), !PAIR);
-    uint32_t* mask = static_cast<uint32_t*>(mask_ws);
-    uint2* words = reinterpret_cast<uint2*>(mask + mask_stride(n) * g.L);
+    const ScatterWs w = scatter_ws(g, level_rows, n);
+    char* ws = static_cast<char*>(mask_ws);
+    ScatterBufs b;
+    b.mask = reinterpret_cast<uint32_t*>(ws);
+    b.words = reinterpret_cast<uint2*>(ws + w.words);
+    b.counts = reinterpret_cast<uint32_t*>(ws + w.counts);
+    b.plan = reinterpret_cast<int4*>(ws + w.plan);
+    b.info = reinterpret_cast<int*>(ws + w.info);
+    b.split = reinterpret_cast<int*>(ws + w.split);
+    b.partials = ws + w.partials;
+    b.extra = w.extra;
+    b.slot_bytes = w.slot_bytes;
     hipLaunchKernelGGL(k_tile_mask<PAIR>, dim3((unsigned)((n + kEncodeBlock - 1) / kEncodeBlock), (unsigned)g.L),
-                       dim3(kEncodeBlock), 0, s, g, tm, reinterpret_cast<const float4*>(xyzt),
-                       reinterpret_cast<const float4*>(eps), n, mask, words);
+                       dim3(kEncodeBlock), 0, s, g, tm,
+                       reinterpret_cast<const float4*>(xyzt), reinterpret_cast<const float4*>(eps), n, b.mask,
+                       b.words, b.counts, w.chunks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // expected queries of a hashed tile, h = n (1 - (1 - 1/P)^8), the largest over the
+    // hashed levels; the plan's first target is 5/4 h
+    double h = 0.0;
+    for (int l = 0; l < g.L; ++l)
+        if (!((g.dense_bits >> l) & 1u))
+            h = std::max(h, n * (1.0 - std::pow(1.0 - 1.0 / (tm.tile_start[l + 1] - tm.tile_start[l]), 8.0)));
+    hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(1024), 0, s, g, tm, b.counts, w.chunks,
+                       (float)std::max(1.25 * h, 1024.0), w.extra, b.plan, b.info, b.split);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     switch (g.F) {
-        case 1:
-            return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, mask, words, src, ls, qs, scale, d_table, overwrite, main, s);
-        case 2:
-            return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, mask, words, src, ls, qs, scale, d_table, overwrite, main, s);
-        case 4:
-            return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, mask, words, src, ls, qs, scale, d_table, overwrite, main, s);
-        case 8:
-            return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, mask, words, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 1: return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 2: return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 4: return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 8: return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, s);
     }
     return hipErrorInvalidValue;
 }

@@ -62,12 +62,12 @@ struct TileMap {
     uint32_t pair_words;
 };
 TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gbytes, bool pair_words = false);
-// Workspace of the scatter: one 32-bit tile mask per (query, level), level-major
-// with the query count padded to a multiple of four so that every level starts on
-// a 16-byte boundary (the scan reads four masks per load); then the per-pair tile
-// bytes, 8 bytes per (query, level), in the same order.
+// The scatter's tile masks: one 32-bit mask per (query, level), level-major with the
+// query count padded to a multiple of four so that every level starts on a 16-byte
+// boundary (the scan reads four masks per load); the per-pair tile bytes follow, 8
+// bytes per (query, level) in the same order, then the load-balance plan.
 constexpr int64_t mask_stride(int64_t n) { return (n + 3) & ~(int64_t)3; }
-size_t scatter_mask_bytes(int n, int L);
+size_t scatter_ws_bytes(const DevGrid& g, const int64_t* level_rows, int n);
 // A second feature gradient for the pair form (eps set): added, times scale, at x's
 // corners only.  src == nullptr: none.
 struct MainGradArg {

@@ -133,10 +133,13 @@ def test_entry_points_validate_without_launching():
     assert lib.hash4d_encode_backward(gp, 0, fake, 0, OW, fake, 1.0, None, fake, 0, None) == -1  # n = 0 writes: NULL
     assert lib.hash4d_encode(gp, 0, fake, fake, 5, OW, fake, None) == -1              # the forward has no gradient
     assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, OW, fake, 1.0, fake, None, 0, None) == -1
-    assert _lib.hash4d_encode_backward_workspace_bytes(g, 1000) == 1000 * 4 * 12
-    # masks (4 bytes) and pair tile bytes (8 bytes) are level-major with the query count
-    # padded to a multiple of four
-    assert _lib.hash4d_encode_backward_workspace_bytes(g, 1001) == 1004 * 4 * 12
+    # masks (4 bytes) and pair tile bytes (8 bytes) per (query, level), level-major with
+    # the query count padded to a multiple of four, then a load-balance plan whose size
+    # does not depend on n within one chunk of queries
+    w1000 = _lib.hash4d_encode_backward_workspace_bytes(g, 1000)
+    w1001 = _lib.hash4d_encode_backward_workspace_bytes(g, 1001)
+    assert w1000 >= 1000 * 4 * 12 and w1001 >= 1004 * 4 * 12
+    assert abs((w1001 - 1004 * 4 * 12) - (w1000 - 1000 * 4 * 12)) <= 512
     assert lib.hash4d_corner_indices(gp, fake, 5, None, None, None) == -1
     assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, 0, fake, 1.0, None, None, 0, None) == -1  # NULL d_xyzt
     assert lib.hash4d_encode_backward_input(gp, 0, fake, fake, 5, 0, fake, 1.0, fake + 8, None, 0, None) == -1
