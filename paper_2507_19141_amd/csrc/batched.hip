@@ -131,14 +131,26 @@ struct BQuery {
 
 constexpr int kBatchScatterBlock = 1024;  // one workgroup per CU (128 KiB tile), 16 wavefronts
 
+// XCD placement of the scatter tiles: the scene-ordered tile list is cut into eight
+// runs of about equal work (queries scanned), run x going to XCD x (workgroup b runs
+// on XCD b % 8), so each XCD's L2 holds the masks, gradients and positions of one or
+// two scenes.
+struct BXcdRuns {
+    int start[kXcds + 1];
+};
+
 template <int F>
 __global__ __launch_bounds__(kBatchScatterBlock) void k_bscatter(const BSeg* __restrict__ segs, const DevGrid* __restrict__ grids,
                                                                  const TileMap* __restrict__ tms,
-                                                                 const BTile* __restrict__ tiles, float scale) {
+                                                                 const BTile* __restrict__ tiles, BXcdRuns runs,
+                                                                 float scale) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int queue[2 * kBatchScatterBlock];
     float* tile = reinterpret_cast<float*>(smem);
-    const BTile tl = tiles[blockIdx.x];
+    const int x = (int)blockIdx.x % kXcds;
+    const int ti = runs.start[x] + (int)blockIdx.x / kXcds;
+    if (ti >= runs.start[x + 1]) return;
+    const BTile tl = tiles[ti];
     const DevGrid& g = grids[tl.scene];
     const TileMap& tm = tms[tl.scene];
     const int l = tl.level;
@@ -198,6 +210,7 @@ struct h4d_batched_plan {
     BRange* ranges_enc = nullptr;
     BTile* tiles = nullptr;
     int ntiles = 0;
+    BXcdRuns xcd_runs{};
     TileMap* tms = nullptr;
     uint32_t* masks = nullptr;
     int max_n = 0, max_L = 0;
@@ -299,13 +312,16 @@ static hipError_t launch_bscatter(const h4d_batched_plan& p, float scale, hipStr
     }
     const int F = p.scenes[0].grid.F;
     const size_t lds = (size_t)kTileBytes;
-    const dim3 grid(p.ntiles), block(kBatchScatterBlock);
+    int longest = 0;
+    for (int x = 0; x < kXcds; ++x) longest = std::max(longest, p.xcd_runs.start[x + 1] - p.xcd_runs.start[x]);
+    const dim3 grid((unsigned)(kXcds * longest)), block(kBatchScatterBlock);
 #define H4D_BSCA(FF)                                                                                             \
     do {                                                                                                         \
         hipError_t e = hipFuncSetAttribute((const void*)k_bscatter<FF>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                            (int)lds);                                                            \
         if (e != hipSuccess) return e;                                                                           \
-        hipLaunchKernelGGL((k_bscatter<FF>), grid, block, lds, st, p.segs, p.grids, p.tms, p.tiles, scale);             \
+        hipLaunchKernelGGL((k_bscatter<FF>), grid, block, lds, st, p.segs, p.grids, p.tms, p.tiles, p.xcd_runs,      \
+                           scale);                                                                               \
     } while (0)
     switch (F) {
         case 1: H4D_BSCA(1); break;
@@ -584,6 +600,19 @@ h4d_status hash4d_batched_plan_create(h4d_batched_plan** out, const h4d_scene_de
             p->max_L = std::max(p->max_L, (int)d.grid.L);
         }
         p->ntiles = (int)tiles.size();
+        // eight runs of about equal work: a tile scans its scene's queries at every timestamp
+        {
+            double total = 0.0;
+            for (const BTile& t : tiles) total += (double)scenes[t.scene].n * t.nseg;
+            double acc = 0.0;
+            int x = 0;
+            p->xcd_runs.start[0] = 0;
+            for (int i = 0; i < (int)tiles.size(); ++i) {
+                acc += (double)scenes[tiles[i].scene].n * tiles[i].nseg;
+                while (x + 1 < kXcds && acc >= total * (x + 1) / kXcds) p->xcd_runs.start[++x] = i + 1;
+            }
+            while (x < kXcds) p->xcd_runs.start[++x] = (int)tiles.size();
+        }
         if ((e = hipMalloc((void**)&p->tiles, std::max<size_t>(1, tiles.size()) * sizeof(BTile))) != hipSuccess ||
             (e = hipMemcpy(p->tiles, tiles.data(), tiles.size() * sizeof(BTile), hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMalloc((void**)&p->tms, tms.size() * sizeof(TileMap))) != hipSuccess ||
