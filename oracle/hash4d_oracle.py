@@ -16,6 +16,7 @@ What it computes (DASH, arXiv 2507.19141):
 * Section 4.2, multi-head deformation decoder and Eq. 10 -- heads for position,
                          rotation and scale, added to the Gaussian attributes.
 * Section 4.3, Eq. 11 -- feature-space smoothness term between x and x + eps.
+* Section 4.1, Eq. 3  -- the 3D hash encoding G_3D of the decomposition step.
 * Training (Eq. 12)   -- the gradients of all of the above with respect to the
                          tables and the decoder weights.
 
@@ -67,6 +68,14 @@ Readings of points the paper leaves open:
      forward selects (lower corner min(floor(x N), N - 1)), d w_c / d x_d =
      (+N_d or -N_d) * prod of the other three factors; zero where the clamp is
      active (x_d < 0, x_d > 1, NaN), the inner one-sided derivative at 0 and 1.
+ R12 G_3D (Section 4.1, Eq. 3), the 3D multiresolution hash encoding of the
+     canonical positions that feeds the motion decoder of the dynamic-static
+     split: the same conventions as G_4D on (x, y, z) alone -- per level the 8
+     corners of the voxel (corner c upper along d iff bit d of c is set), the
+     first three primes of R4, a level stored densely iff its (N+1)^3 vertices fit
+     in T rows, trilinear weights.  Levels follow Eq. 7 with the spatial
+     (N_min, N_max).  phi_p then phi_l of Eq. 3 are read as the decoder trunk and
+     one 3-output head (Delta p).
 
 Parity pins live in tests/test_oracle_*.py; "parity unpinned" marks what no pin
 covers (the prime set itself: any fixed set of large primes is a correct reading).
@@ -285,6 +294,102 @@ def encode_backward_input(xyzt: np.ndarray, table: np.ndarray, grid: Grid, d_fea
             tg = np.sum(th[rows[:, l, c]] * gl, axis=1)
             out += dw[:, l, c, :] * tg[:, None]
     return scale * out
+
+
+# ----------------------------------------------------------------------------
+# Encoder G_3D -- Section 4.1, Eq. 3 (reading R12)
+# ----------------------------------------------------------------------------
+@dataclass
+class Grid3:
+    L: int
+    F: int
+    res: list              # resolution per level (the same along x, y and z)
+    T: int                 # hash table rows per hashed level
+    dense: list = field(default_factory=list)
+    sizes: list = field(default_factory=list)
+    offsets: list = field(default_factory=list)   # first row of each level, length L+1
+
+    @property
+    def E(self) -> int:
+        return self.offsets[-1]
+
+
+def make_grid3(L, F, res, T) -> Grid3:
+    """Per-level rows of G_3D: dense iff (N+1)^3 <= T (R12), else T rows."""
+    g = Grid3(L=L, F=F, res=[int(r) for r in res], T=int(T))
+    off = 0
+    g.offsets.append(0)
+    for l in range(L):
+        nv = (g.res[l] + 1) ** 3
+        d = nv <= g.T
+        g.dense.append(d)
+        g.sizes.append(nv if d else g.T)
+        off += g.sizes[-1]
+        g.offsets.append(off)
+    return g
+
+
+def dense_index3(vx, vy, vz, N: int) -> np.ndarray:
+    """Collision-free row of vertex (vx, vy, vz) on a dense 3D level, x fastest."""
+    S = N + 1
+    return vx + S * (vy + S * vz)
+
+
+def hash_index3(vx, vy, vz, T: int) -> np.ndarray:
+    """The spatial hash of the 3D encoding: (XOR_d v_d * pi_d) mod T over x, y, z,
+    products and XOR wrapped to 32 bits (R4, R12)."""
+    h = np.zeros(np.shape(vx), dtype=np.uint64)
+    for v, p in zip((vx, vy, vz), PRIMES[:3]):
+        h ^= (np.asarray(v, dtype=np.uint64) * np.uint64(p)) & np.uint64(MASK32)
+    return (h % np.uint64(T)).astype(np.int64)
+
+
+def corners3(xyz: np.ndarray, grid: Grid3):
+    """Rows [n, L, 8] (level offset included) and weights [n, L, 8] FP64 of the 8
+    voxel corners at every level; corner c is upper along d iff bit d of c is set."""
+    x32 = clamp_unit_f32(np.asarray(xyz, dtype=np.float32)[:, :3])
+    n = x32.shape[0]
+    rows = np.zeros((n, grid.L, 8), dtype=np.int64)
+    wts = np.zeros((n, grid.L, 8), dtype=np.float64)
+    for l in range(grid.L):
+        N = grid.res[l]
+        lo, fr = zip(*(cell_position(x32[:, d], N) for d in range(3)))
+        for c in range(8):
+            up = [(c >> d) & 1 for d in range(3)]
+            v = [lo[d] + up[d] for d in range(3)]
+            w = np.ones(n, dtype=np.float64)
+            for d in range(3):
+                w = w * (fr[d] if up[d] else 1.0 - fr[d])
+            idx = dense_index3(v[0], v[1], v[2], N) if grid.dense[l] else hash_index3(v[0], v[1], v[2], grid.T)
+            rows[:, l, c] = grid.offsets[l] + idx
+            wts[:, l, c] = w
+    return rows, wts
+
+
+def encode3(xyz: np.ndarray, table: np.ndarray, grid: Grid3) -> np.ndarray:
+    """G_3D(p) in R^{L F}: per level sum_c w_c theta[row_c], levels concatenated (FP64)."""
+    rows, wts = corners3(xyz, grid)
+    th = np.asarray(table, dtype=np.float64)
+    n = rows.shape[0]
+    out = np.zeros((n, grid.L * grid.F), dtype=np.float64)
+    for l in range(grid.L):
+        acc = np.zeros((n, grid.F), dtype=np.float64)
+        for c in range(8):
+            acc += wts[:, l, c:c + 1] * th[rows[:, l, c]]
+        out[:, l * grid.F:(l + 1) * grid.F] = acc
+    return out
+
+
+def encode3_backward(xyz: np.ndarray, d_feat: np.ndarray, grid: Grid3, scale: float = 1.0) -> np.ndarray:
+    """Transpose of encode3: d_theta[row_c] += scale * w_c * d_feat_l.  [E, F] FP64."""
+    rows, wts = corners3(xyz, grid)
+    g = np.asarray(d_feat, dtype=np.float64)
+    out = np.zeros((grid.E, grid.F), dtype=np.float64)
+    for l in range(grid.L):
+        gl = g[:, l * grid.F:(l + 1) * grid.F]
+        for c in range(8):
+            np.add.at(out, rows[:, l, c], scale * wts[:, l, c:c + 1] * gl)
+    return out
 
 
 # ----------------------------------------------------------------------------

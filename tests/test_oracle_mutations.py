@@ -188,3 +188,47 @@ def test_split_taking_ties_as_dynamic_is_caught(monkeypatch):
         return np.nonzero(dyn)[0], 0.0, np.zeros((n, 3))
     monkeypatch.setattr(O, "decompose", ties_up)
     expect_pin_failure(Dec.test_split_matches_brute_force_with_ties_and_nan)
+
+
+# ---- G_3D (reading R12) ----
+from tests import test_oracle_encoder3 as E3  # noqa: E402
+
+
+def test_g3d_slab_dense_criterion_is_caught(monkeypatch):
+    # the 4D encoder on a t = 0 slab with one temporal cell: dense iff 2 (N+1)^3 <= T
+    real = O.make_grid3
+
+    def slab(L, F, res, T):
+        g = real(L, F, res, T)
+        off = [0]
+        g.dense, g.sizes = [], []
+        for N in g.res:
+            nv = 2 * (N + 1) ** 3
+            g.dense.append(nv <= g.T)
+            g.sizes.append(nv if nv <= g.T else g.T)
+            off.append(off[-1] + g.sizes[-1])
+        g.offsets = off
+        return g
+    monkeypatch.setattr(O, "make_grid3", slab)
+    expect_pin_failure(E3.test_dense_threshold_is_the_3d_vertex_count)
+
+
+def test_g3d_swapped_primes_are_caught(monkeypatch):
+    def swapped(vx, vy, vz, T):   # pi_2 and pi_3 exchanged
+        h = np.zeros(np.shape(vx), dtype=np.uint64)
+        for v, p in zip((vx, vy, vz), (O.PRIMES[0], O.PRIMES[2], O.PRIMES[1])):
+            h ^= (np.asarray(v, dtype=np.uint64) * np.uint64(p)) & np.uint64(O.MASK32)
+        return (h % np.uint64(T)).astype(np.int64)
+    monkeypatch.setattr(O, "hash_index3", swapped)
+    expect_pin_failure(E3.test_hash_matches_python_integers, 1 << 19)
+    expect_pin_failure(E3.test_brute_force_exact_on_tiny_hashed_grid)
+
+
+def test_g3d_corner_bits_out_of_step_are_caught(monkeypatch):
+    real = O.cell_position
+
+    def swapped(x32, N):   # the upper corner given the lower corner's weight
+        i, fr = real(x32, N)
+        return i, 1.0 - fr
+    monkeypatch.setattr(O, "cell_position", swapped)
+    expect_pin_failure(E3.test_dense_level_matches_scipy_trilinear)
