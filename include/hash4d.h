@@ -85,6 +85,22 @@ typedef struct {
     uint32_t prime[4];                  /* hash multipliers for x, y, z, t */
 } h4d_grid;
 
+/* Multiresolution 3D grid of G_3D (Section 4.1, Eq. 3): the hash encoding of the
+ * canonical positions that feeds the motion decoder of the dynamic-static split.
+ * Host struct, filled by h4d_grid3_init.  Level l has resolution res[l] along x,
+ * y and z, so (res+1)^3 vertices; a level whose vertices fit in T rows is stored
+ * densely (x fastest, then y, z), every other level is hashed into T rows with the
+ * first three primes of the 4D grid.  Table [E, F], E = offset[L]. */
+typedef struct {
+    int32_t L;                          /* levels, 1..32 */
+    int32_t F;                          /* features per row: 1, 2, 4 or 8 */
+    int64_t T;                          /* rows of a hashed level, 1..2^30 */
+    int32_t res[H4D_MAX_LEVELS];        /* 1..2^24 */
+    int64_t offset[H4D_MAX_LEVELS + 1]; /* first row of each level; offset[L] = E */
+    uint8_t dense[H4D_MAX_LEVELS];      /* 1 = dense level */
+    uint32_t prime[3];                  /* hash multipliers for x, y, z */
+} h4d_grid3;
+
 /* Decoder shape (Section 4.2, Eq. 9 and the multi-head decoder).  in = L F,
  * hidden = 64, out = 10 (dx 3 | drot 4 | dscale 3).  Parameters are one flat
  * array in the order W1[hidden, in], b1[hidden], W2[hidden, hidden], b2[hidden],
@@ -129,6 +145,23 @@ int64_t h4d_grid_rows(const h4d_grid* g);
  * Written, not accumulated.  Deterministic (no atomics). */
 h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* table,
                          const float* xyzt, int64_t n, h4d_layout layout, void* feat, void* stream);
+
+/* Fill *g (host) for G_3D from explicit per-level resolutions (host array of L
+ * values): dense iff (res+1)^3 <= T, offsets, primes (1, 2654435761, 805459861).
+ * EINVAL on any out-of-range field or if E F >= 2^31. */
+h4d_status h4d_grid3_init(h4d_grid3* g, int32_t L, int32_t F, const int32_t* res, int64_t T);
+
+/* The 3D encoder G_3D of Section 4.1 (Eq. 3): per position and level, scale by the
+ * level resolution in FP32 (as hash4d_encode does), take the 8 corners of the
+ * voxel, gather F features per corner and interpolate trilinearly; positions are
+ * clamped to [0, 1] (NaN to 0).
+ *   table  [E, F] of table_dt (F32, BF16 bit patterns, or F64)
+ *   xyz    n rows of `stride` FP32 values (3: [n, 3]; 4: [n, 4] with the fourth
+ *          ignored, 16-byte aligned), x, y, z first
+ *   feat   n L F values in `layout`; FP32 for F32/BF16 tables, FP64 for F64.
+ * Written, not accumulated.  Deterministic (no atomics). */
+h4d_status hash3d_encode(const h4d_grid3* g, h4d_dtype table_dt, const void* table, const float* xyz,
+                         int32_t stride, int64_t n, h4d_layout layout, void* feat, void* stream);
 
 /* Backward of hash4d_encode with respect to the table (the exact transpose of the
  * interpolation in Eq. 9): d_table[row_c, f] += grad_scale * w_c * d_feat[q, l F + f]

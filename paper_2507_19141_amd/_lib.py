@@ -45,6 +45,23 @@ class Grid(ctypes.Structure):
         return [int(self.offset[l]) for l in range(self.L + 1)]
 
 
+class Grid3(ctypes.Structure):
+    """Mirror of h4d_grid3."""
+    _fields_ = [("L", ctypes.c_int32), ("F", ctypes.c_int32), ("T", ctypes.c_int64),
+                ("res", ctypes.c_int32 * MAX_LEVELS), ("offset", ctypes.c_int64 * (MAX_LEVELS + 1)),
+                ("dense", ctypes.c_uint8 * MAX_LEVELS), ("prime", ctypes.c_uint32 * 3)]
+
+    @property
+    def E(self) -> int:
+        return int(self.offset[self.L])
+
+    def dense_list(self) -> list:
+        return [bool(self.dense[l]) for l in range(self.L)]
+
+    def offsets(self) -> list:
+        return [int(self.offset[l]) for l in range(self.L + 1)]
+
+
 class Mlp(ctypes.Structure):
     """Mirror of h4d_mlp."""
     _fields_ = [("in_", ctypes.c_int32), ("hidden", ctypes.c_int32), ("out", ctypes.c_int32)]
@@ -86,6 +103,7 @@ _P = ctypes.c_void_p
 _I32, _I64, _F32, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
 _GP = ctypes.POINTER(Grid)
 _MP = ctypes.POINTER(Mlp)
+_G3P = ctypes.POINTER(Grid3)
 
 # name -> (restype, argtypes); the order follows include/hash4d.h
 SIGNATURES = {
@@ -93,6 +111,8 @@ SIGNATURES = {
     "h4d_version": (ctypes.c_char_p, []),
     "h4d_grid_schedule": (_I32, [_I32, _I32, _I32, _I32, ctypes.POINTER(_I32)]),
     "h4d_grid_init": (_I32, [_GP, _I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _I64]),
+    "h4d_grid3_init": (_I32, [_G3P, _I32, _I32, ctypes.POINTER(_I32), _I64]),
+    "hash3d_encode": (_I32, [_G3P, _I32, _P, _P, _I32, _I64, _I32, _P, _P]),
     "h4d_grid_rows": (_I64, [_GP]),
     "hash4d_encode": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _P]),
     "hash4d_encode_backward_workspace_bytes": (_SZ, [_GP, _I64]),
@@ -198,6 +218,13 @@ def h4d_grid_init(L: int, F: int, res_s, res_t, T: int) -> Grid:
     return g
 
 
+def h4d_grid3_init(L: int, F: int, res, T: int) -> Grid3:
+    g = Grid3()
+    r = (_I32 * L)(*[int(v) for v in res])
+    _check("h4d_grid3_init", load().h4d_grid3_init(ctypes.byref(g), L, F, r, T))
+    return g
+
+
 def h4d_grid_rows(g: Grid) -> int:
     return int(load().h4d_grid_rows(ctypes.byref(g)))
 
@@ -206,6 +233,12 @@ def h4d_grid_rows(g: Grid) -> int:
 def hash4d_encode(g: Grid, table_dt: int, table, xyzt, n: int, feat, layout: int = QUERY_MAJOR,
                   stream=None) -> None:
     _check("hash4d_encode", load().hash4d_encode(ctypes.byref(g), table_dt, ptr(table), ptr(xyzt), n, layout,
+                                                 ptr(feat), stream_handle(stream)))
+
+
+def hash3d_encode(g: Grid3, table_dt: int, table, xyz, stride: int, n: int, feat, layout: int = QUERY_MAJOR,
+                  stream=None) -> None:
+    _check("hash3d_encode", load().hash3d_encode(ctypes.byref(g), table_dt, ptr(table), ptr(xyz), stride, n, layout,
                                                  ptr(feat), stream_handle(stream)))
 
 

@@ -70,6 +70,45 @@ static h4d_status check_grid(const h4d_grid* g) {
     return H4D_OK;
 }
 
+// The 3D grid of G_3D: every field in range and the derived fields consistent.
+static h4d_status check_grid3(const h4d_grid3* g) {
+    if (!g) return fail(H4D_EINVAL, "grid3 pointer is NULL");
+    if (g->L < 1 || g->L > H4D_MAX_LEVELS) return fail(H4D_EINVAL, "grid3: L=%d outside 1..%d", g->L, H4D_MAX_LEVELS);
+    if (!valid_F(g->F)) return fail(H4D_EINVAL, "grid3: F=%d not in {1,2,4,8}", g->F);
+    if (g->T < 1 || g->T > kMaxT) return fail(H4D_EINVAL, "grid3: T=%lld outside 1..2^30", (long long)g->T);
+    if (g->offset[0] != 0) return fail(H4D_EINVAL, "grid3: offset[0] != 0 (struct not initialised?)");
+    for (int l = 0; l < g->L; ++l) {
+        if (g->res[l] < 1 || g->res[l] > kMaxRes)
+            return fail(H4D_EINVAL, "grid3: level %d resolution %d outside 1..2^24", l, g->res[l]);
+        const int64_t S = (int64_t)g->res[l] + 1;
+        const unsigned __int128 v = (unsigned __int128)S * S * S;
+        const bool dense = v <= (unsigned __int128)g->T;
+        if ((g->dense[l] != 0) != dense || g->offset[l + 1] - g->offset[l] != (dense ? (int64_t)v : g->T))
+            return fail(H4D_EINVAL, "grid3: level %d layout inconsistent with its resolution (re-run h4d_grid3_init)", l);
+    }
+    if (g->offset[g->L] * g->F >= ((int64_t)1 << 31))
+        return fail(H4D_EINVAL, "grid3: table of %lld rows x %d features exceeds 2^31 elements",
+                    (long long)g->offset[g->L], g->F);
+    return H4D_OK;
+}
+
+static DevGrid3 to_device3(const h4d_grid3& g) {
+    DevGrid3 d;
+    memset(&d, 0, sizeof d);
+    d.L = g.L;
+    d.F = g.F;
+    d.T = (uint32_t)g.T;
+    d.tmask = ((g.T & (g.T - 1)) == 0 && g.T > 1) ? (uint32_t)(g.T - 1) : 0u;
+    for (int k = 0; k < 3; ++k) d.prime[k] = g.prime[k];
+    for (int l = 0; l < g.L; ++l) {
+        d.res[l] = g.res[l];
+        d.off[l] = (uint32_t)g.offset[l];
+        if (g.dense[l]) d.dense_bits |= 1u << l;
+    }
+    d.rows = (uint32_t)g.offset[g.L];
+    return d;
+}
+
 // Rows of each level of a validated grid.
 static void rows_of(const h4d_grid& g, int64_t* rows) {
     for (int l = 0; l < g.L; ++l) rows[l] = g.offset[l + 1] - g.offset[l];
@@ -220,6 +259,39 @@ h4d_status h4d_grid_init(h4d_grid* g, int32_t L, int32_t F, const int32_t* res_s
     return H4D_OK;
 }
 
+h4d_status h4d_grid3_init(h4d_grid3* g, int32_t L, int32_t F, const int32_t* res, int64_t T) {
+    g_last_error.clear();
+    if (!g || !res) return fail(H4D_EINVAL, "NULL argument");
+    memset(g, 0, sizeof *g);
+    if (L < 1 || L > H4D_MAX_LEVELS) return fail(H4D_EINVAL, "L=%d outside 1..%d", L, H4D_MAX_LEVELS);
+    if (!valid_F(F)) return fail(H4D_EINVAL, "F=%d not in {1,2,4,8}", F);
+    if (T < 1 || T > kMaxT) return fail(H4D_EINVAL, "T=%lld outside 1..2^30", (long long)T);
+    g->L = L;
+    g->F = F;
+    g->T = T;
+    for (int k = 0; k < 3; ++k) g->prime[k] = kPrimes[k];
+    int64_t off = 0;
+    for (int l = 0; l < L; ++l) {
+        if (res[l] < 1 || res[l] > kMaxRes) {
+            memset(g, 0, sizeof *g);
+            return fail(H4D_EINVAL, "level %d resolution %d outside 1..2^24", l, res[l]);
+        }
+        g->res[l] = res[l];
+        const int64_t S = (int64_t)res[l] + 1;
+        const unsigned __int128 v = (unsigned __int128)S * S * S;
+        const bool dense = v <= (unsigned __int128)T;
+        g->dense[l] = dense ? 1 : 0;
+        g->offset[l] = off;
+        off += dense ? (int64_t)v : T;
+    }
+    g->offset[L] = off;
+    if (off * F >= ((int64_t)1 << 31)) {
+        memset(g, 0, sizeof *g);
+        return fail(H4D_EINVAL, "table of %lld rows x %d features exceeds 2^31 elements", (long long)off, F);
+    }
+    return H4D_OK;
+}
+
 int64_t h4d_grid_rows(const h4d_grid* g) {
     if (check_grid(g) != H4D_OK) return -1;
     return g->offset[g->L];
@@ -253,6 +325,25 @@ h4d_status hash4d_encode(const h4d_grid* g, h4d_dtype table_dt, const void* tabl
     const DevGrid d = to_device(*g);
     return hip_status(launch_encode(d, table_dt, table, xyzt, (int)n, feat, ls, qs, (hipStream_t)stream),
                       "hash4d_encode");
+}
+
+h4d_status hash3d_encode(const h4d_grid3* g, h4d_dtype table_dt, const void* table, const float* xyz,
+                         int32_t stride, int64_t n, h4d_layout layout, void* feat, void* stream) {
+    g_last_error.clear();
+    h4d_status st;
+    int64_t ls, qs;
+    if ((st = check_grid3(g)) || (st = check_dtype(table_dt))) return st;
+    if (stride != 3 && stride != 4) return fail(H4D_EINVAL, "stride=%d, must be 3 or 4", stride);
+    if (n < 0 || n > kMaxQ) return fail(H4D_EINVAL, "n=%lld outside 0..2^31-2^16", (long long)n);
+    if ((st = feat_strides(layout, n, g->L, g->F, &ls, &qs))) return st;
+    if (n == 0) return H4D_OK;
+    if (!table || !xyz || !feat) return fail(H4D_EINVAL, "table, xyz or feat is NULL");
+    if (((uintptr_t)xyz) & (stride == 4 ? 15u : 3u))
+        return fail(H4D_EINVAL, "xyz is not aligned to %d bytes", stride == 4 ? 16 : 4);
+    if ((st = check_table_alignment(table, table_dt, g->F))) return st;
+    return hip_status(launch_encode3(to_device3(*g), table_dt, table, xyz, stride, (int)n, feat, ls, qs,
+                                     (hipStream_t)stream),
+                      "hash3d_encode");
 }
 
 size_t hash4d_encode_backward_workspace_bytes(const h4d_grid* g, int64_t n) {

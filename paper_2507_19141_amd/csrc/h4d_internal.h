@@ -23,6 +23,23 @@ struct DevGrid {
     uint32_t rows;                // E, rows of the whole table
 };
 
+// The 3D grid of G_3D as its kernel sees it (passed by value).
+struct DevGrid3 {
+    int32_t L;
+    int32_t F;
+    uint32_t T;
+    uint32_t tmask;      // T - 1 when T is a power of two, else 0
+    uint32_t dense_bits; // bit l set: level l is dense
+    uint32_t prime[3];
+    int32_t res[H4D_MAX_LEVELS];
+    uint32_t off[H4D_MAX_LEVELS];
+    uint32_t rows;       // E
+};
+// G_3D forward (encode3.hip): xyz rows of `stride` (3 or 4) floats, x y z first;
+// out[l lstride + q qstride + f].
+hipError_t launch_encode3(const DevGrid3& g, h4d_dtype dt, const void* table, const float* xyz, int stride, int n,
+                          void* out, int64_t lstride, int64_t qstride, hipStream_t s);
+
 // Host-side conversion of a validated h4d_grid.
 DevGrid to_device(const h4d_grid& g);
 // Full validation of a caller-provided grid (sets the thread's last error).

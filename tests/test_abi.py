@@ -228,3 +228,35 @@ def test_query_count_limit_boundary():
     assert "outside" in _lib.last_error()
     assert lib.hash4d_deform_apply(None, limit + 1, 10, fake, fake, fake, fake, fake, fake, None) == -1
     assert "outside" in _lib.last_error()
+
+
+def test_grid3_layout_matches_oracle():
+    rng = np.random.default_rng(33)
+    for _ in range(200):
+        L = int(rng.integers(1, 17))
+        F = int(rng.choice([1, 2, 4, 8]))
+        T = int(rng.choice([1 << int(rng.integers(4, 21)), int(rng.integers(1, 1 << 20))]))
+        res = sorted(int(v) for v in rng.integers(1, 300, size=L))
+        og = O.make_grid3(L, F, res, T)
+        if og.E * F >= 1 << 31:
+            continue
+        lg = _lib.h4d_grid3_init(L, F, res, T)
+        assert lg.dense_list() == og.dense and lg.offsets() == og.offsets
+        assert list(lg.prime) == list(O.PRIMES[:3])
+
+
+def test_hash3d_encode_validates_without_launching():
+    lib = _lib.load()
+    g = _lib.h4d_grid3_init(3, 2, [4, 8, 16], 1 << 10)
+    gp = _lib.ctypes.byref(g)
+    fake = 1 << 20   # never dereferenced: validation fails first
+    assert lib.hash3d_encode(gp, 0, fake, fake, 3, 0, 0, fake, None) == 0        # n = 0: no-op
+    assert lib.hash3d_encode(gp, 0, fake, fake, 5, 4, 0, fake, None) == -1       # stride
+    assert "stride" in _lib.last_error()
+    assert lib.hash3d_encode(gp, 0, None, fake, 3, 4, 0, fake, None) == -1       # NULL table
+    assert lib.hash3d_encode(gp, 0, fake, fake + 4, 4, 4, 0, fake, None) == -1   # [n, 4] rows not 16-byte aligned
+    assert lib.hash3d_encode(gp, 0, fake, fake + 2, 3, 4, 0, fake, None) == -1   # not 4-byte aligned
+    assert lib.hash3d_encode(gp, 0, fake, fake, 3, -1, 0, fake, None) == -1      # negative n
+    g.offset[2] += 1
+    assert lib.hash3d_encode(gp, 0, fake, fake, 3, 4, 0, fake, None) == -1       # corrupted grid
+    assert "inconsistent" in _lib.last_error()

@@ -81,26 +81,25 @@ def test_split_small_and_ragged_sizes():
 
 
 def test_front_end_chain():
-    # the whole front end on the paper-shaped cloud: a 3D multiresolution hash encoding
-    # of the positions (the 4D encoder on the t = 0 slab with one temporal cell, whose
-    # time term hashes to 0: the 3D hash of Eq. 8's first three primes), a 32-64-64-3
-    # decoder for dp (phi_p then phi_l), and the split on the decoder's FP32 output
+    # the whole front end on the paper-shaped cloud: the 3D multiresolution hash
+    # encoding G_3D of the positions (Eq. 3), a 32-64-64-3 decoder for dp (phi_p then
+    # phi_l), and the split on the decoder's FP32 output
     import torch
     w = synth.PAPER_SCENE
     n = 50_000
     rng, x = synth.scene_inputs(n, 85)
-    x[:, 3] = 0.0
     rs = _lib.h4d_grid_schedule(w.L, *w.space)
-    g = _lib.h4d_grid_init(w.L, w.F, rs, [1] * w.L, w.T)
-    og = O.make_grid(w.L, w.F, list(rs), [1] * w.L, w.T)
+    g = _lib.h4d_grid3_init(w.L, w.F, rs, w.T)
+    og = O.make_grid3(w.L, w.F, list(rs), w.T)
+    assert g.offsets() == og.offsets
     table = synth.table_init(og.E, w.F, rng, 1e-1)
     params = synth.decoder_params(w.n_in, rng, out=3)
     feat = torch.empty((n, w.L * w.F), device="cuda")
-    _lib.hash4d_encode(g, _lib.F32, dev(table), dev(x), n, feat)
+    _lib.hash3d_encode(g, _lib.F32, dev(table), dev(x), 4, n, feat)
     m = _lib.mlp_shape(w.n_in, out=3)
     dp = torch.empty((n, 3), device="cuda")
     _lib.deform_mlp_forward(m, _lib.F32, dev(params), feat, n, dp)
-    f_ref = O.encode(x, table, og)
+    f_ref = O.encode3(x, table, og)
     P = O.unpack_params(params, w.n_in, out=3)
     h1 = np.maximum(f_ref @ P["W1"].T + P["b1"], 0)
     h2 = np.maximum(h1 @ P["W2"].T + P["b2"], 0)
