@@ -32,7 +32,7 @@ KERNEL_SOURCES = ("encode.hip", "h4d_device.h", "h4d_internal.h", "mlp.hip")
 # the library kernels behind each timed part of the step
 STEP_KERNELS = {"cast": ["k_cast_bf16"], "encode": ["k_encode"], "decode": ["k_mlp_forward"],
                 "decode_bwd": ["k_mlp_frags", "k_mlp_backward", "k_mlp_reduce"],
-                "scatter": ["k_tile_mask", "k_scatter_tiled"]}
+                "scatter": ["k_tile_mask", "k_tile_plan", "k_scatter_tiled", "k_tile_combine"]}
 TRAFFIC_FILE = os.path.join("profiles", "traffic_deform_paper_scene_fp32.md")
 
 
@@ -216,6 +216,14 @@ def probes(torch, _lib, E, F, n_loads, reps=5):
     out["scatter8_xcd_owned_GBps"] = n_loads * 8 / t / 1e9
     t = timed(lambda: _lib.h4d_probe_scatter(buf, 1 << 17, n_loads, 9, 0))
     out["scatter8_1MiB_GBps"] = n_loads * 8 / t / 1e9
+    # random 8-byte gathers over 4 MiB: the footprint one XCD's L2 holds, which is
+    # what the level-placed encoder presents to each XCD
+    t = timed(lambda: _lib.h4d_probe_gather(buf, 1 << 19, 8, n_loads, 7, sink))
+    out["gather8_4MiB_Gloads_per_s"] = n_loads / t / 1e9
+    # LDS compare-and-swap adds: 512 workgroups x 1024 threads x 256 adds each
+    per, blocks = 256, 512
+    t = timed(lambda: _lib.h4d_probe_lds_atomic(blocks, per, 64, 3, 2, sink))
+    out["lds_cas_G_per_s"] = blocks * 1024 * per / t / 1e9
     nbytes = 1 << 30
     src = torch.empty(nbytes // 4, device="cuda")
     dst = torch.empty_like(src)
@@ -271,6 +279,73 @@ def probe_sweep(torch, _lib, E, n_loads, reps=5):
     return out
 
 
+def scatter_tile_count(rows_per_level, F=2, gbytes=4):
+    """Tiles of the table scatter: per level about 32 tiles of a power of two of rows,
+    at least 256 rows and at most 128 KiB of gradient."""
+    max_rows = (128 * 1024) // (F * gbytes)
+    tiles = 0
+    for r in rows_per_level:
+        want = -(-r // 32)
+        sh = 8
+        while (1 << sh) < max_rows and (1 << sh) < want:
+            sh += 1
+        tiles += -(-r // (1 << sh))
+    return tiles
+
+
+def achievable(torch, _lib, synth, per, pr, n):
+    """Each kernel's time against the probe ceiling that matches its access pattern
+    (each fraction at most 1 when the kernel runs at that ceiling):
+    encode: its corner-row requests (one per x-pair whose rows are an aligned pair,
+    two otherwise, counted from the corner rows) at the random-gather request rate of
+    a 4 MiB, L2-resident footprint (the level slice each XCD holds);
+    scatter: the owner-computes floor, the larger of the time to stream every tile's
+    level of query masks at the copy rate and the time for the corner updates at the
+    LDS compare-and-swap rate (the queries' own loads taken as free)."""
+    w = synth.PAPER_SCENE
+    g = _lib.h4d_grid_init(w.L, w.F, _lib.h4d_grid_schedule(w.L, *w.space), _lib.h4d_grid_schedule(w.L, *w.time),
+                           w.T)
+    _, x = synth.scene_inputs(w.n, 0)
+    rows = torch.empty((n, w.L, 16), dtype=torch.int32, device="cuda")
+    _lib.hash4d_corner_indices(g, torch.from_numpy(x).cuda(), n, rows, None)
+    r0, r1 = rows[..., 0::2], rows[..., 1::2]
+    paired = (r1 == (r0 ^ 1)) & ((r0 | 1) < g.E)
+    requests = int(n * w.L * 8 + (~paired).sum().item())
+    del rows, r0, r1, paired
+    t_enc = requests / (pr["gather8_4MiB_Gloads_per_s"] * 1e9)
+    level_rows = [g.offsets()[l + 1] - g.offsets()[l] for l in range(w.L)]
+    tiles = scatter_tile_count(level_rows)
+    mask_stream = tiles * n * 4                        # every tile scans its level's masks
+    t_scan = mask_stream / (pr["copy_GBps"] * 1e9)
+    t_lds = n * w.L * 16 / (pr["lds_cas_G_per_s"] * 1e9)
+    t_sca = max(t_scan, t_lds)
+    enc_ms, sca_ms = per["encode"], per["scatter"]
+    return {"encode": {"requests": requests, "probe": "gather8_4MiB_Gloads_per_s", "floor_ms": t_enc * 1e3,
+                       "ms": enc_ms, "frac": t_enc * 1e3 / enc_ms},
+            "scatter": {"tiles": tiles, "mask_stream_bytes": mask_stream, "scan_floor_ms": t_scan * 1e3,
+                        "lds_floor_ms": t_lds * 1e3, "floor_ms": t_sca * 1e3, "ms": sca_ms,
+                        "frac": t_sca * 1e3 / sca_ms}}
+
+
+def _oracle_levels(job):
+    """One level of the oracle's encode (forward) or table gradient (backward), for the
+    all-core CPU baseline: the oracle's own functions on a one-level grid."""
+    import numpy as np
+    from oracle import hash4d_oracle as O
+    kind, l = job
+    st = _CPU_STATE
+    g = st["g"]
+    gl = O.make_grid(1, g.F, [g.res_s[l]], [g.res_t[l]], g.T)
+    sl = slice(g.offsets[l], g.offsets[l + 1])
+    if kind == "fwd":
+        return O.encode(st["x"], st["table"][sl], gl)
+    d_feat = st["d_feat"][:, l * g.F:(l + 1) * g.F]
+    return O.encode_backward(st["x"], np.ascontiguousarray(d_feat), gl)
+
+
+_CPU_STATE = {}
+
+
 def cpu_baseline(sample: int):
     import numpy as np
     from threadpoolctl import threadpool_limits
@@ -288,10 +363,33 @@ def cpu_baseline(sample: int):
         t0 = time.perf_counter()
         O.deform_forward(xs, table, g, params)
         O.deform_backward(xs, table, g, params, gs)
-        dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample} of the {w.n} clustered queries (all of them by default), full tables; FP64 oracle forward "
-                      f"(f_h, delta) + backward (d_table, d_params) in {dt:.1f} s, 1 thread"}
+        dt1 = time.perf_counter() - t0
+    # all cores: the levels of the encoder and its table gradient in a process pool
+    # (their rows are disjoint), the decoder with BLAS on every core; at most 16
+    # workers, the host share one GPU has
+    import multiprocessing as mp
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    _CPU_STATE.update({"g": g, "x": xs, "table": table})
+    t0 = time.perf_counter()
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        f_h = np.concatenate(pool.map(_oracle_levels, [("fwd", l) for l in range(g.L)]), axis=1)
+        with threadpool_limits(limits=cores):
+            delta, _ = O.mlp_forward(params, f_h)
+            d_feat, d_params = O.mlp_backward(params, f_h, gs)
+        _CPU_STATE["d_feat"] = d_feat
+    with ctx.Pool(cores) as pool:
+        parts = pool.map(_oracle_levels, [("bwd", l) for l in range(g.L)])
+        d_table = np.concatenate(parts, axis=0)
+    dtn = time.perf_counter() - t0
+    _CPU_STATE.clear()
+    assert d_table.shape == (g.E, g.F) and delta.shape == (sample, 10) and d_params.size > 0
+    return {"value": sample / dtn, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "one_thread_value": sample / dt1,
+            "sample": f"first {sample} of the {w.n} clustered queries (all of them by default), full tables; FP64 "
+                      f"oracle forward (f_h, delta) + backward (d_table, d_params): {dtn:.1f} s on {cores} cores (the "
+                      f"encoder's levels in a process pool, the decoder with {cores} BLAS threads), {dt1:.1f} s on "
+                      f"1 thread"}
 
 
 def batched_form(torch, _lib, synth, steps: int, warmup: int):
@@ -669,18 +767,7 @@ def main():
                                _lib.h4d_grid_schedule(w.L, *w.time), w.T).E
         pr = probes(torch, _lib, E, w.F, n * 16 * w.L)
         result["probes"] = pr
-        # step-level fraction of the probe ceilings (gathers at the random-gather rate,
-        # scatter at the random-atomic rate, everything else at the copy rate)
-        L, F = w.L, w.F
-        gather_b, scatter_b = 16 * L * F * 4, 16 * L * F * 4
-        stream_b = sum(ab.values()) - gather_b - scatter_b
-        t_roof = n * (gather_b / (pr["gather8_GBps"] * 1e9) + scatter_b / (pr["scatter8_GBps"] * 1e9)
-                      + stream_b / (pr["copy_GBps"] * 1e9))
-        result["achievable_frac"] = t_roof / (gpu_ms / 1e3)
-        result["achievable_note"] = ("probe ceilings: corner gathers at the random 8-byte gather rate over the "
-                                     "table, corner updates at the random device-atomic rate, the rest at the copy "
-                                     "rate; above 1 where the kernels beat a probe (the scatter uses no device "
-                                     "atomics)")
+        result["achievable"] = achievable(torch, _lib, synth, per, pr, n)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(result), flush=True)
