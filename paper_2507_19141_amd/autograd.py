@@ -3,7 +3,8 @@
 ``DeformField`` describes one scene's field (grid, decoder shape, precision form);
 ``Hash4DDeform.apply(xyzt, table, params, field, scaler)`` returns the decoder output
 delta = [dx | drot | dscale] (DASH Section 4.2) and routes its backward through the
-library's decoder backward and table scatter; ``SmoothnessReg.apply(xyzt, eps,
+library's decoder backward and table scatter (and, when the positions require a
+gradient, the encoder's input gradient); ``SmoothnessReg.apply(xyzt, eps,
 table, field, lam)`` returns the Eq. 11 regulariser, whose table gradient the
 library computes in the same pass as the loss.
 
@@ -46,28 +47,50 @@ class Hash4DDeform(torch.autograd.Function):
         feat = torch.empty((g.L, n, g.F), dtype=field.torch_dtype, device=xyzt.device)
         delta = torch.empty((n, m.out), dtype=field.torch_dtype, device=xyzt.device)
         _lib.hash4d_deform_forward(g, m, field.dtype, t_used, p_used, xyzt, n, feat, delta)
-        ctx.save_for_backward(xyzt, feat, p_used)
+        ctx.save_for_backward(xyzt, feat, p_used, t_used)
         ctx.field, ctx.scaler = field, scaler
         ctx.table_shape, ctx.n_params = tuple(table.shape), params.numel()
         return delta
 
     @staticmethod
     def backward(ctx, d_delta):
-        xyzt, feat, p_used = ctx.saved_tensors
+        xyzt, feat, p_used, t_used = ctx.saved_tensors
         field, scaler = ctx.field, ctx.scaler
         g, m = field.grid, field.mlp
         n = xyzt.shape[0]
+        dev = xyzt.device
         S = scaler.scale if scaler is not None else 1.0
-        d_table = torch.zeros(ctx.table_shape, dtype=field.torch_dtype, device=xyzt.device)
-        d_params = torch.zeros(ctx.n_params, dtype=field.torch_dtype, device=xyzt.device)
-        ws_bytes = _lib.hash4d_deform_workspace_bytes(g, m, field.dtype, n)
-        ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=xyzt.device)
-        _lib.hash4d_deform_backward(g, m, field.dtype, p_used, xyzt, n, feat,
-                                    d_delta.to(field.torch_dtype).contiguous(), S, 1.0 / S, d_table, d_params,
-                                    ws, ws_bytes)
+        d_table = torch.zeros(ctx.table_shape, dtype=field.torch_dtype, device=dev)
+        d_params = torch.zeros(ctx.n_params, dtype=field.torch_dtype, device=dev)
+        d_delta = d_delta.to(field.torch_dtype).contiguous()
+        if not ctx.needs_input_grad[0]:
+            ws_bytes = _lib.hash4d_deform_workspace_bytes(g, m, field.dtype, n)
+            ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+            _lib.hash4d_deform_backward(g, m, field.dtype, p_used, xyzt, n, feat, d_delta, S, 1.0 / S, d_table,
+                                        d_params, ws, ws_bytes)
+            d_xyzt = None
+        else:
+            # the positions need their gradient too (the derivative of Eq. 9 with
+            # respect to x): decoder backward, then the table scatter and the input
+            # gradient from the same (unscaled) feature gradient
+            LM = _lib.LEVEL_MAJOR
+            d_feat = torch.empty((g.L, n, g.F), dtype=field.torch_dtype, device=dev)
+            wb = _lib.deform_mlp_workspace_bytes(m, field.dtype, n)
+            ws = torch.empty(max(wb, 1), dtype=torch.uint8, device=dev)
+            _lib.deform_mlp_backward(m, field.dtype, p_used, feat, n, d_delta, S, 1.0 / S, d_feat, d_params, ws, wb,
+                                     LM, g.F)
+            grad_dt = _lib.F64 if field.dtype == _lib.F64 else _lib.F32
+            wb = _lib.hash4d_encode_backward_workspace_bytes(g, n)
+            ws = torch.empty(max(wb, 1), dtype=torch.uint8, device=dev)
+            _lib.hash4d_encode_backward(g, grad_dt, xyzt, n, d_feat, 1.0, d_table, ws, wb, LM)
+            d_xyzt = torch.zeros((n, 4), dtype=field.torch_dtype, device=dev)
+            wb = _lib.hash4d_encode_backward_input_workspace_bytes(g, field.dtype, n)
+            ws = torch.empty(max(wb, 1), dtype=torch.uint8, device=dev) if wb else None
+            _lib.hash4d_encode_backward_input(g, field.dtype, t_used, xyzt, n, d_feat, 1.0, d_xyzt, LM, ws, wb)
+            d_xyzt = d_xyzt.to(xyzt.dtype)
         if scaler is not None:
             scaler.observe(d_table, d_params)
-        return None, d_table, d_params, None, None
+        return d_xyzt, d_table, d_params, None, None
 
 
 class SmoothnessReg(torch.autograd.Function):

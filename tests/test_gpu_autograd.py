@@ -230,3 +230,25 @@ def test_bf16_form_with_dynamic_loss_scale():
     (delta * bad).sum().backward()
     assert scaler.update() is False
     assert scaler.scale == 2.0 ** 11 and scaler.skipped == 1
+
+
+def test_autograd_position_gradient_matches_oracle_chain():
+    # positions that require a gradient get d delta / d x through the encoder's input
+    # gradient (the derivative of Eq. 9), against the oracle's chain of the decoder
+    # backward and the encoder input gradient; table and decoder gradients unchanged
+    from paper_2507_19141_amd.autograd import Hash4DDeform
+    from tests.test_gpu_input_grad import magnitude
+    w, og, lg, x, table, params, gd, _ = smooth_case(3000, 203)
+    xd = dev(x).requires_grad_(True)
+    t = dev(table).requires_grad_(True)
+    p = dev(params).requires_grad_(True)
+    delta = Hash4DDeform.apply(xd, t, p, field(lg, w.n_in, _lib.F32), None)
+    (delta * dev(gd)).sum().backward()
+    f_ref = O.encode(x, table, og)
+    rf, rp = O.mlp_backward(params, f_ref, gd)
+    sf, sp = mlp_backward_scale(params, f_ref, gd)
+    ref = O.encode_backward_input(x, table, og, rf)
+    scaled_close(host(xd.grad), ref, magnitude(x, table, og, sf), RTOL_GRAD, "autograd d_xyzt")
+    scaled_close(host(t.grad), O.encode_backward(x, rf, og), O.encode_backward(x, sf, og), RTOL_GRAD,
+                 "autograd d_table (position path)")
+    scaled_close(host(p.grad), rp, sp, RTOL_GRAD, "autograd d_params (position path)")
