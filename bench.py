@@ -517,7 +517,7 @@ def smoothness_form(torch, _lib, synth, path, steps: int):
         torch.cuda.synchronize()
         step_ms["one_scatter" if merged else "separate"] = a.elapsed_time(b) / steps
     return {"ms": ms, "value": n / (ms / 1e3), "unit": "queries/s", "lambda": 1.0, "sigma": 1e-3,
-            "kernels": ["k_smooth", "k_tile_mask", "k_scatter_tiled"],
+            "kernels": ["k_smooth", "k_tile_mask", "k_tile_plan", "k_scatter_tiled", "k_tile_combine"],
             "training_step_ms": step_ms, "training_step_value": n / (step_ms["one_scatter"] / 1e3)}
 
 
