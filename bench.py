@@ -31,7 +31,7 @@ HBM_PEAK_GBPS = 8000.0
 KERNEL_SOURCES = ("encode.hip", "h4d_device.h", "h4d_internal.h", "mlp.hip")
 # the library kernels behind each timed part of the step
 STEP_KERNELS = {"cast": ["k_cast_bf16"], "encode": ["k_encode"], "decode": ["k_mlp_forward"],
-                "decode_bwd": ["k_mlp_frags", "k_mlp_backward", "k_mlp_reduce"],
+                "decode_bwd": ["k_mlp_backward", "k_mlp_reduce"],
                 "scatter": ["k_tile_mask", "k_tile_plan", "k_scatter_tiled", "k_tile_combine"]}
 TRAFFIC_FILE = os.path.join("profiles", "traffic_deform_paper_scene_fp32.md")
 
@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--counters", action="store_true",
                     help="a few FP32 steps plus one 256 MiB copy kernel (the calibration reference of the "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE passes); prints the step kernels' names")
+    ap.add_argument("--counters-form", default="fp32", choices=("fp32", "bf16"),
+                    help="the form the --counters run steps")
     ap.add_argument("--probe-sweep", action="store_true",
                     help="only run the gather / atomic probes over several footprints and print them")
     ap.add_argument("--cpu-sample", type=int, default=200000, help="queries the CPU oracle is timed on")
@@ -693,14 +695,14 @@ def main():
     torch.cuda.set_device(0)
     _lib.load()
     if args.counters:
-        fp = Path(torch, _lib, synth, "fp32")
+        fp = Path(torch, _lib, synth, args.counters_form)
         fp.run(max(1, args.steps), 1)
         nbytes = 256 << 20
         src = torch.ones(nbytes // 4, device="cuda")
         dst = torch.empty_like(src)
         _lib.h4d_probe_copy(src, dst, nbytes)
         torch.cuda.synchronize()
-        print(json.dumps({"counters_run": {"steps": args.steps + 1, "copy_bytes": nbytes,
+        print(json.dumps({"counters_run": {"form": args.counters_form, "steps": args.steps + 1, "copy_bytes": nbytes,
                                            "copy_kernel": "k_probe_copy"}}), flush=True)
         return
     if args.probe_sweep:

@@ -159,8 +159,8 @@ struct MlpBatch {
 
 // Persistent-grid size of the decoder kernels for a total of `queries` queries.
 int mlp_blocks_for(h4d_dtype dt, bool backward, int64_t queries);
-// Workspace of the decoder backward for a grid of `blocks` workgroups over `spans`
-// parameter sets: per-block partial rows, then one fragment table per span.
+// Workspace of the decoder backward for a grid of `blocks` workgroups: one partial
+// row of the parameter gradient per workgroup (`spans` does not change it).
 size_t mlp_partial_bytes(h4d_dtype dt, int in, int out, int blocks, int spans);
 hipError_t launch_mlp_forward_batch(h4d_dtype dt, int in, int out, const MlpBatch& b, int blocks, hipStream_t s);
 hipError_t launch_mlp_backward_batch(h4d_dtype dt, int in, int out, const MlpBatch& b, int blocks, double in_scale,

@@ -37,10 +37,14 @@ constexpr int HID = H4D_HIDDEN;
 constexpr int OUTP = H4D_MAX_OUT;
 constexpr int kMlpBlock = 256;
 constexpr int kWaves = kMlpBlock / 64;
-constexpr int kTbStride = 17;  // LDS transpose buffer row stride (2-cycle wave64 access)
-constexpr int kTbRows = 128;
 
 __device__ __forceinline__ int hid(int idx, int kb) { return 16 * (idx >> 2) + 4 * kb + (idx & 3); }
+
+// Wait for every vector memory operation of this wavefront (s_waitcnt vmcnt(0)).
+// Called before a tile loop whose first tile's inputs were loaded ahead, so that the
+// compiler sees no load of the loop's entry still in flight at the loop head and does
+// not make the first products of every iteration wait on that iteration's prefetch.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0f70); }
 
 struct dacc {
     double v[4];
@@ -133,17 +137,6 @@ struct Shape {
     static constexpr int NCO = KO / KC;
     static constexpr int NO = KO / 4;                       // upstream gradients held per lane
     static constexpr int MF = (IN + 15) / 16;               // 16-row tiles of d_feat
-    // fragment tables, in elements: [tiles][chunks][64 lanes][E]
-    static constexpr int A1 = 4 * NC1 * 64 * E;   // W1      (layer 1, forward)
-    static constexpr int A2 = 4 * NCH * 64 * E;   // W2
-    static constexpr int A3 = 1 * NCH * 64 * E;   // W3
-    static constexpr int B3 = 4 * NCO * 64 * E;   // W3^T    (backward)
-    static constexpr int B2 = 4 * NCH * 64 * E;   // W2^T
-    static constexpr int B1 = MF * NCH * 64 * E;  // W1^T
-    static constexpr int OFF_A1 = 0, OFF_A2 = OFF_A1 + A1, OFF_A3 = OFF_A2 + A2, OFF_B3 = OFF_A3 + A3,
-                         OFF_B2 = OFF_B3 + B3, OFF_B1 = OFF_B2 + B2;
-    static constexpr int FWD_FRAGS = OFF_B3;
-    static constexpr int ALL_FRAGS = OFF_B1 + B1;
 };
 
 // Parameter offsets in the flat array.
@@ -160,73 +153,82 @@ struct ParamOff {
     }
 };
 
-// Flat parameter index of fragment element t of the tables (-1 = zero padding).
+// Fragment tables, one per matrix operand of the layer chain: A1, A2, A3 (forward:
+// W1, W2, W3) and B3, B2, B1 (backward: W3^T, W2^T, W1^T).  Matrix m has tiles(m)
+// 16-row tiles and nc(m) K chunks of E elements per lane.  A table is cut into units
+// of grp(m) consecutive chunks of one tile; inside a unit lane l's grp(m) E elements
+// lie together, so that one LDS read (16 bytes for FP32, whose units hold four
+// chunks, and for BF16) fetches the operands of grp(m) products.
+enum { kA1 = 0, kA2, kA3, kB3, kB2, kB1, kMats };
+
 template <class Pol, int IN>
-__device__ int frag_source(int t, int out, const ParamOff& po) {
+struct Tab {
+    using Sh = Shape<Pol, IN>;
+    static constexpr int E = Pol::E;
+    __host__ __device__ static constexpr int nc(int m) { return m == kA1 ? Sh::NC1 : m == kB3 ? Sh::NCO : Sh::NCH; }
+    __host__ __device__ static constexpr int tiles(int m) { return m == kA3 ? 1 : m == kB1 ? Sh::MF : 4; }
+    __host__ __device__ static constexpr int grp(int m) {
+        return E > 1 ? 1 : nc(m) % 4 == 0 ? 4 : nc(m) % 2 == 0 ? 2 : 1;
+    }
+    __host__ __device__ static constexpr int size(int m) { return tiles(m) * nc(m) * 64 * E; }
+    __host__ __device__ static constexpr int off(int m) { return m == 0 ? 0 : off(m - 1) + size(m - 1); }
+    // table position of element e of chunk c of tile mt, lane `lane`
+    __host__ __device__ static constexpr int at(int m, int mt, int c, int lane, int e) {
+        return off(m) + ((mt * (nc(m) / grp(m)) + c / grp(m)) * 64 + lane) * grp(m) * E + (c % grp(m)) * E + e;
+    }
+    static constexpr int FWD = off(kB3);   // forward tables: A1 A2 A3
+    static constexpr int ALL = off(kMats);
+};
+
+// Flat parameter index of element e of chunk c of tile mt of matrix m for lane
+// (i, kb) (-1 = zero padding).
+template <class Pol, int IN>
+__device__ __forceinline__ int frag_param(int m, int mt, int c, int lane, int e, int out, const ParamOff& po) {
     using Sh = Shape<Pol, IN>;
     constexpr int E = Sh::E;
-    int mat, rel;
-    if (t < Sh::OFF_A2) { mat = 0; rel = t - Sh::OFF_A1; }
-    else if (t < Sh::OFF_A3) { mat = 1; rel = t - Sh::OFF_A2; }
-    else if (t < Sh::OFF_B3) { mat = 2; rel = t - Sh::OFF_A3; }
-    else if (t < Sh::OFF_B2) { mat = 3; rel = t - Sh::OFF_B3; }
-    else if (t < Sh::OFF_B1) { mat = 4; rel = t - Sh::OFF_B2; }
-    else { mat = 5; rel = t - Sh::OFF_B1; }
-    const int e = rel % E;
-    const int lane = (rel / E) % 64;
-    const int tc = rel / (E * 64);  // tile * chunks + chunk
     const int i = lane & 15, kb = lane >> 4;
-    switch (mat) {
-        case 0: {  // A1[mt][c]: W1[16 mt + i][kb NI + c E + e]
-            const int mt = tc / Sh::NC1, c = tc % Sh::NC1;
+    switch (m) {
+        case kA1: {  // W1[16 mt + i][kb NI + c E + e]
             const int k = kb * Sh::NI + c * E + e;
             return k < IN ? po.W1 + (16 * mt + i) * IN + k : -1;
         }
-        case 1: {  // A2[mt][c]: W2[16 mt + i][hid(c E + e, kb)]
-            const int mt = tc / Sh::NCH, c = tc % Sh::NCH;
+        case kA2:  // W2[16 mt + i][hid(c E + e, kb)]
             return po.W2 + (16 * mt + i) * HID + hid(c * E + e, kb);
-        }
-        case 2: {  // A3[c]: W3[i][hid(c E + e, kb)]
-            const int c = tc;
+        case kA3:  // W3[i][hid(c E + e, kb)]
             return i < out ? po.W3 + i * HID + hid(c * E + e, kb) : -1;
-        }
-        case 3: {  // B3[mt][c]: W3^T -> W3[kb NO + c E + e][16 mt + i]
-            const int mt = tc / Sh::NCO, c = tc % Sh::NCO;
+        case kB3: {  // W3^T: W3[kb NO + c E + e][16 mt + i]
             const int o = kb * Sh::NO + c * E + e;
             return o < out ? po.W3 + o * HID + 16 * mt + i : -1;
         }
-        case 4: {  // B2[mt][c]: W2^T -> W2[hid(c E + e, kb)][16 mt + i]
-            const int mt = tc / Sh::NCH, c = tc % Sh::NCH;
+        case kB2:  // W2^T: W2[hid(c E + e, kb)][16 mt + i]
             return po.W2 + hid(c * E + e, kb) * HID + 16 * mt + i;
-        }
-        default: {  // B1[mf][c]: W1^T -> W1[hid(c E + e, kb)][16 mf + i]
-            const int mf = tc / Sh::NCH, c = tc % Sh::NCH;
-            const int f = 16 * mf + i;
+        default: {  // W1^T: W1[hid(c E + e, kb)][16 mt + i]
+            const int f = 16 * mt + i;
             return f < IN ? po.W1 + hid(c * E + e, kb) * IN + f : -1;
         }
     }
 }
 
-// Fragment tables: built in LDS for FP32 / BF16; read straight from the
+// Fragment operands: from the LDS tables for FP32 / BF16; straight from the
 // parameter array for FP64 (its tables would not fit next to its other buffers).
 template <class Pol, int IN, bool LDS>
 struct Frags {
     using FE = typename Pol::FE;
+    using TB = Tab<Pol, IN>;
     const FE* lds;                         // LDS tables (LDS == true)
     const typename Pol::S* params;         // global parameters (LDS == false)
     int out;
     ParamOff po;
 
-    __device__ typename Pol::Op get(int off, int tc) const {
+    __device__ typename Pol::Op get(int m, int mt, int c) const {
         const int lane = threadIdx.x & 63;
         if constexpr (LDS) {
-            return Pol::frag(lds + ((size_t)(off / Pol::E + tc * 64 + lane)) * Pol::E);
+            return Pol::frag(lds + TB::at(m, mt, c, lane, 0));
         } else {
             FE v[Pol::E];
 #pragma unroll
             for (int e = 0; e < Pol::E; ++e) {
-                const int t = off + (tc * 64 + lane) * Pol::E + e;
-                const int s = frag_source<Pol, IN>(t, out, po);
+                const int s = frag_param<Pol, IN>(m, mt, c, lane, e, out, po);
                 v[e] = s >= 0 ? Pol::to_frag(params[s]) : FE(0);
             }
             return Pol::frag(v);
@@ -234,41 +236,52 @@ struct Frags {
     }
 };
 
-template <class Pol, int IN>
-__device__ void fill_frags(typename Pol::FE* lds, int count, const typename Pol::S* __restrict__ params, int out,
-                           const ParamOff& po) {
-    // The permutation reads the (L2-resident) parameters directly, eight independent
-    // loads in flight per thread before their LDS stores.
-    constexpr int B = 8;
-    for (int t0 = threadIdx.x; t0 < count; t0 += B * blockDim.x) {
-        typename Pol::FE v[B];
+// Builds the LDS table of matrix M: wavefront-strided over its units, each lane
+// gathering its grp E (L2-resident) parameters and storing them together.
+template <class Pol, int IN, int M>
+__device__ __forceinline__ void fill_table(typename Pol::FE* lds, const typename Pol::S* __restrict__ params, int out,
+                                           const ParamOff& po) {
+    using TB = Tab<Pol, IN>;
+    using FE = typename Pol::FE;
+    constexpr int G = TB::grp(M), GE = G * Pol::E, NCG = TB::nc(M) / G, UNITS = TB::tiles(M) * NCG;
+    const int lane = threadIdx.x & 63, nw = (int)(blockDim.x >> 6);
+    for (int u = (int)(threadIdx.x >> 6); u < UNITS; u += nw) {
+        const int mt = u / NCG, c0 = (u % NCG) * G;
+        FE v[GE];
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            const int t = t0 + k * (int)blockDim.x;
-            const int s = t < count ? frag_source<Pol, IN>(t, out, po) : -1;
-            v[k] = s >= 0 ? Pol::to_frag(params[s]) : typename Pol::FE(0);
-        }
+        for (int cc = 0; cc < G; ++cc)
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            const int t = t0 + k * (int)blockDim.x;
-            if (t < count) lds[t] = v[k];
+            for (int e = 0; e < Pol::E; ++e) {
+                const int s = frag_param<Pol, IN>(M, mt, c0 + cc, lane, e, out, po);
+                v[cc * Pol::E + e] = s >= 0 ? Pol::to_frag(params[s]) : FE(0);
+            }
+        FE* dst = lds + TB::at(M, mt, c0, lane, 0);
+        if constexpr (sizeof(v) == 16) {
+            *reinterpret_cast<uint4*>(dst) = __builtin_bit_cast(uint4, v);
+        } else if constexpr (sizeof(v) == 8) {
+            *reinterpret_cast<uint2*>(dst) = __builtin_bit_cast(uint2, v);
+        } else {
+#pragma unroll
+            for (int k = 0; k < GE; ++k) dst[k] = v[k];
         }
     }
 }
 
-// The backward's fragment tables of every span, built once per call into the
-// workspace (a workgroup per 256 elements and span); each backward workgroup then
-// copies its span's tables into LDS instead of rebuilding them.
 template <class Pol, int IN>
-__global__ __launch_bounds__(256) void k_mlp_frags(MlpBatch b, int out, typename Pol::FE* __restrict__ frags,
-                                                   int64_t stride) {
-    using Sh = Shape<Pol, IN>;
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= Sh::ALL_FRAGS) return;
-    const typename Pol::S* __restrict__ params = static_cast<const typename Pol::S*>(b.s[blockIdx.y].params);
-    const ParamOff po(IN, out);
-    const int s = frag_source<Pol, IN>(t, out, po);
-    frags[(int64_t)blockIdx.y * stride + t] = s >= 0 ? Pol::to_frag(params[s]) : typename Pol::FE(0);
+__device__ void fill_forward_tables(typename Pol::FE* lds, const typename Pol::S* __restrict__ params, int out,
+                                    const ParamOff& po) {
+    fill_table<Pol, IN, kA1>(lds, params, out, po);
+    fill_table<Pol, IN, kA2>(lds, params, out, po);
+    fill_table<Pol, IN, kA3>(lds, params, out, po);
+}
+
+template <class Pol, int IN>
+__device__ void fill_all_tables(typename Pol::FE* lds, const typename Pol::S* __restrict__ params, int out,
+                                const ParamOff& po) {
+    fill_forward_tables<Pol, IN>(lds, params, out, po);
+    fill_table<Pol, IN, kB3>(lds, params, out, po);
+    fill_table<Pol, IN, kB2>(lds, params, out, po);
+    fill_table<Pol, IN, kB1>(lds, params, out, po);
 }
 
 __device__ __forceinline__ int span_of_block(const MlpBatch& b) {
@@ -285,42 +298,72 @@ struct Bias {
     double d1[16], d2[16], d3[4];
 };
 
+// Accumulator tile mt of hidden layer 1 or 2 initialised to the layer's biases
+// (lane (j, kb) holds rows 16 mt + 4 kb + r), from per-lane registers ...
+template <class Pol>
+struct RegBias {
+    const typename Pol::V (&b1)[16];
+    const typename Pol::V (&b2)[16];
+    __device__ typename Pol::Acc init(int layer, int mt) const {
+        const typename Pol::V* b = layer == 1 ? b1 : b2;
+        typename Pol::Acc a;
+        if constexpr (std::is_same<Pol, PolF64>::value) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a.v[r] = b[mt * 4 + r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = b[mt * 4 + r];
+        }
+        return a;
+    }
+};
+
+// ... or from LDS: b1 at lds[0, 64), b2 at lds[64, 128).
+template <class Pol>
+struct LdsBias {
+    const typename Pol::V* lds;
+    __device__ typename Pol::Acc init(int layer, int mt) const {
+        const typename Pol::V* p = lds + 64 * (layer - 1) + 16 * mt + 4 * ((threadIdx.x & 63) >> 4);
+        if constexpr (std::is_same<Pol, PolF64>::value) return dacc{{p[0], p[1], p[2], p[3]}};
+        else return *reinterpret_cast<const floatx4*>(p);
+    }
+};
+
 // Forward through the trunk for one tile: returns H1, H2 in accumulator order.
-template <class Pol, int IN, class FR>
+template <class Pol, int IN, class FR, class BS>
 __device__ __forceinline__ void trunk_forward(const FR& fr, const typename Pol::V (&fv)[Shape<Pol, IN>::NI],
-                                              const typename Pol::V (&b1)[16], const typename Pol::V (&b2)[16],
-                                              typename Pol::V (&h1)[16], typename Pol::V (&h2)[16]) {
+                                              const BS& bs, typename Pol::V (&h1)[16], typename Pol::V (&h2)[16]) {
     using Sh = Shape<Pol, IN>;
     using V = typename Pol::V;
     typename Pol::Acc a[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::zero();
+    for (int mt = 0; mt < 4; ++mt) a[mt] = bs.init(1, mt);
 #pragma unroll
     for (int c = 0; c < Sh::NC1; ++c) {
         const typename Pol::Op b = Pol::pack(&fv[c * Sh::E]);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::mma(fr.get(Sh::OFF_A1, mt * Sh::NC1 + c), b, a[mt]);
+        for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::mma(fr.get(kA1, mt, c), b, a[mt]);
     }
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const V z = (V)Pol::get(a[mt], r) + b1[mt * 4 + r];
+            const V z = (V)Pol::get(a[mt], r);
             h1[mt * 4 + r] = z > V(0) ? z : V(0);
         }
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::zero();
+    for (int mt = 0; mt < 4; ++mt) a[mt] = bs.init(2, mt);
 #pragma unroll
     for (int c = 0; c < Sh::NCH; ++c) {
         const typename Pol::Op b = Pol::pack(&h1[c * Sh::E]);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::mma(fr.get(Sh::OFF_A2, mt * Sh::NCH + c), b, a[mt]);
+        for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::mma(fr.get(kA2, mt, c), b, a[mt]);
     }
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const V z = (V)Pol::get(a[mt], r) + b2[mt * 4 + r];
+            const V z = (V)Pol::get(a[mt], r);
             h2[mt * 4 + r] = z > V(0) ? z : V(0);
         }
 }
@@ -371,7 +414,7 @@ void k_mlp_forward(MlpBatch batch, int out) {
     const ParamOff po(IN, out);
     Frags<Pol, IN, kLds> fr{reinterpret_cast<const typename Pol::FE*>(smem), params, out, po};
     if constexpr (kLds)  // no staging buffer: the forward keeps its LDS small for occupancy
-        fill_frags<Pol, IN>(reinterpret_cast<typename Pol::FE*>(smem), Sh::FWD_FRAGS, params, out, po);
+        fill_forward_tables<Pol, IN>(reinterpret_cast<typename Pol::FE*>(smem), params, out, po);
     __syncthreads();
     V b1[16], b2[16], b3[4];
     load_biases<Pol>(params, po, out, b1, b2, b3);
@@ -390,6 +433,7 @@ void k_mlp_forward(MlpBatch batch, int out) {
     int tile = ((int)blockIdx.x - sp.block0) * kWaves + (int)(threadIdx.x >> 6);
     V next[Sh::NI];
     load_tile(tile, next);
+    wait_vmem();
     for (; tile < ntiles; tile += stride) {
         // Weight fragments are read from LDS at each use rather than held in registers
         // across the loop: the smaller register footprint fits four wavefronts per SIMD.
@@ -401,12 +445,12 @@ void k_mlp_forward(MlpBatch batch, int out) {
         V fv[Sh::NI];
 #pragma unroll
         for (int i = 0; i < Sh::NI; ++i) fv[i] = next[i];
-        load_tile(tile + stride, next);
         V h1[16], h2[16];
-        trunk_forward<Pol, IN>(fr, fv, b1, b2, h1, h2);
+        trunk_forward<Pol, IN>(fr, fv, RegBias<Pol>{b1, b2}, h1, h2);
+        load_tile(tile + stride, next);
         typename Pol::Acc a3 = Pol::zero();
 #pragma unroll
-        for (int c = 0; c < Sh::NCH; ++c) a3 = Pol::mma(fr.get(Sh::OFF_A3, c), Pol::pack(&h2[c * Sh::E]), a3);
+        for (int c = 0; c < Sh::NCH; ++c) a3 = Pol::mma(fr.get(kA3, 0, c), Pol::pack(&h2[c * Sh::E]), a3);
         if (valid) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -418,105 +462,171 @@ void k_mlp_forward(MlpBatch batch, int out) {
 }
 
 // --------------------------------------------------------------- backward ----
-// Weight-gradient operands over the 16 queries of a tile.  For the 16x16 block
-// whose rows start at row r0 of the transpose buffer, lane (i, kb) holds the
-// values of row r0 + i at the queries it contributes: q = 4c + kb for chunk c
-// (FP32 / FP64, four 16x16x4 products) or q = 4kb + e (BF16, one 16x16x16 product).
+// A workgroup of NW wavefronts takes NW tiles (Q = 16 NW queries) per iteration.
+// Each wavefront runs the layer chain of its own tile: the trunk recomputed, then
+// the transposed backward through W3, W2 and W1, which gives d_feat.  The weight
+// gradients contract over queries instead.  For those the chain values of the NW
+// tiles are written transposed into a shared staging buffer (one row per unit, one
+// column per query), and every 16x16 block of dW3, dW2 and dW1 has one owner
+// wavefront, which contracts it over all Q queries and keeps it in registers
+// across iterations.  A wavefront so holds 1/NW of the weight gradient, and every
+// parameter's sum is formed by one wavefront in a fixed order.
+//
+// Staging: a row holds Q queries (padded), so that a lane reads one operand group
+// (4 queries for the 16x16x4 products, 8 for the 16x16x32 BF16 product) with one
+// 16-byte LDS read.  Query q of group m goes to K slot kb when q = QG m + (QG/4) kb
+// + e; any assignment works as long as both operands use it.
 template <class Pol>
-struct WOp {
-    typename Pol::V v[4];
+struct Stage;
+
+template <>
+struct Stage<PolF32> {
+    using T = float;
+    static constexpr int QG = 16, PAD = 4;
+    struct Grp {
+        floatx4 v;
+    };
+    __device__ static void put(T* p, float v) { *p = v; }
+    __device__ static Grp load(const T* row, int m) {
+        return Grp{*reinterpret_cast<const floatx4*>(row + QG * m + 4 * ((threadIdx.x & 63) >> 4))};
+    }
+    __device__ static void mma(floatx4& acc, const Grp& a, const Grp& b) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[e], b.v[e], acc, 0, 0, 0);
+    }
+    __device__ static float sum(const Grp& a) { return (a.v[0] + a.v[1]) + (a.v[2] + a.v[3]); }
 };
 
-template <class Pol>
-__device__ __forceinline__ WOp<Pol> wload(const typename Pol::V* tb, int r0) {
-    const int lane = threadIdx.x & 63, i = lane & 15, kb = lane >> 4;
-    WOp<Pol> o;
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-        o.v[c] = std::is_same<Pol, PolBF16>::value ? tb[(r0 + i) * kTbStride + 4 * kb + c]
-                                                   : tb[(r0 + i) * kTbStride + 4 * c + kb];
-    return o;
-}
-
-// acc[i][j] += sum_q A[q][i] B[q][j] over the tile's 16 queries.
-template <class Pol>
-__device__ __forceinline__ void wmma(typename Pol::Acc& acc, const WOp<Pol>& a, const WOp<Pol>& b) {
-    if constexpr (std::is_same<Pol, PolBF16>::value) {
-        shortx4 x, y;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            x[e] = __builtin_bit_cast(short, (__bf16)a.v[e]);
-            y[e] = __builtin_bit_cast(short, (__bf16)b.v[e]);
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, acc, 0, 0, 0);
-    } else {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc = Pol::mma(a.v[c], b.v[c], acc);
+template <>
+struct Stage<PolBF16> {
+    using T = uint16_t;  // BF16 bit patterns, rounded to nearest even once when staged
+    static constexpr int QG = 32, PAD = 8;
+    struct Grp {
+        bf16x8 v;
+    };
+    __device__ static void put(T* p, float v) { *p = __builtin_bit_cast(uint16_t, (__bf16)v); }
+    __device__ static Grp load(const T* row, int m) {
+        return Grp{__builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const ushortx8*>(row + QG * m + 8 * ((threadIdx.x & 63) >> 4)))};
     }
-}
+    __device__ static void mma(floatx4& acc, const Grp& a, const Grp& b) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
+    }
+    __device__ static float sum(const Grp& a) {
+        float t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = (float)a.v[2 * e] + (float)a.v[2 * e + 1];
+        return (t[0] + t[1]) + (t[2] + t[3]);
+    }
+};
+
+template <>
+struct Stage<PolF64> {
+    using T = double;
+    static constexpr int QG = 16, PAD = 2;
+    struct Grp {
+        double v[4];
+    };
+    __device__ static void put(T* p, double v) { *p = v; }
+    __device__ static Grp load(const T* row, int m) {
+        const T* p = row + QG * m + 4 * ((threadIdx.x & 63) >> 4);
+        return Grp{{p[0], p[1], p[2], p[3]}};
+    }
+    __device__ static void mma(dacc& acc, const Grp& a, const Grp& b) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = PolF64::mma(a.v[e], b.v[e], acc);
+    }
+    __device__ static double sum(const Grp& a) { return (a.v[0] + a.v[1]) + (a.v[2] + a.v[3]); }
+};
+
+constexpr size_t kLdsBudget = 160 * 1024;
 
 template <class Pol, int IN>
-__global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int out, typename Pol::V in_scale,
-                                                            typename Pol::V feat_scale,
-                                                            typename Pol::G* __restrict__ partial,
-                                                            const typename Pol::FE* __restrict__ frags,
-                                                            int64_t frag_stride) {
+struct Bwd {
     using Sh = Shape<Pol, IN>;
+    using St = Stage<Pol>;
+    static constexpr bool kLds = !std::is_same<Pol, PolF64>::value;
+    static constexpr int MF = Sh::MF;
+    // stage 1 rows: G3^T | H2^T | G1^T | F^T; stage 2 rows: G2^T | H1^T
+    static constexpr int R_G3 = 0, R_H2 = 16, R_G1 = 80, R_F = 144, ROWS = 144 + 16 * MF;
+    static constexpr int R_G2 = 0, R_H1 = 64;
+    static constexpr size_t kFragBytes =
+        kLds ? ((size_t)Tab<Pol, IN>::ALL * sizeof(typename Pol::FE) + 15) / 16 * 16 : 0;
+    static constexpr size_t kBiasBytes = 128 * sizeof(typename Pol::V);  // b1 | b2
+    static constexpr size_t stage_bytes(int nw) { return (size_t)ROWS * (16 * nw + St::PAD) * sizeof(typename St::T); }
+    static constexpr int NW = kFragBytes + kBiasBytes + stage_bytes(8) <= kLdsBudget ? 8 : 4;
+    static constexpr int Q = 16 * NW;
+    static constexpr int S = Q + St::PAD;            // staging row stride, elements
+    static constexpr int NG = Q / St::QG;            // operand groups per contraction
+    static constexpr size_t kLdsBytes = kFragBytes + kBiasBytes + stage_bytes(NW);
+    static constexpr int B2 = 16 / NW;               // dW2 blocks per wavefront (one row tile)
+    static constexpr int B1 = (4 * MF + NW - 1) / NW;  // dW1 blocks per wavefront (strided)
+    static_assert(kLdsBytes <= kLdsBudget, "backward LDS");
+    static_assert((S * sizeof(typename St::T)) % 16 == 0, "16-byte aligned staging rows");
+};
+
+template <class Pol, int IN>
+constexpr int bwd_threads() { return 64 * Bwd<Pol, IN>::NW; }
+
+template <class Pol, int IN>
+__global__ __launch_bounds__((bwd_threads<Pol, IN>())) void k_mlp_backward(MlpBatch batch, int out,
+                                                                          typename Pol::V in_scale,
+                                                                          typename Pol::V feat_scale,
+                                                                          typename Pol::G* __restrict__ partial) {
+    using C = Bwd<Pol, IN>;
+    using Sh = Shape<Pol, IN>;
+    using St = Stage<Pol>;
+    using T = typename St::T;
     using V = typename Pol::V;
     using G = typename Pol::G;
     using Acc = typename Pol::Acc;
-    constexpr bool kLds = !std::is_same<Pol, PolF64>::value;
+    constexpr int NW = C::NW, S = C::S;
+    constexpr bool kLds = C::kLds;
     extern __shared__ __align__(16) unsigned char smem[];
     const int span = span_of_block(batch);
     const MlpSpan& sp = batch.s[span];
     const typename Pol::S* __restrict__ params = static_cast<const typename Pol::S*>(sp.params);
     const ParamOff po(IN, out);
-    // LDS: [fragment tables (FP32/BF16 only)][block gradient accumulator (FP32/BF16 only)][transpose buffers]
+    // LDS: [fragment tables (FP32/BF16 only)][b1 | b2][staging buffer]
     typename Pol::FE* frag_lds = reinterpret_cast<typename Pol::FE*>(smem);
-    size_t off = kLds ? ((size_t)Sh::ALL_FRAGS * sizeof(typename Pol::FE) + 15) / 16 * 16 : 0;
-    G* wacc = reinterpret_cast<G*>(smem + off);
-    if (kLds) off += ((size_t)po.P * sizeof(G) + 15) / 16 * 16;
-    V* tb = reinterpret_cast<V*>(smem + off) + (threadIdx.x >> 6) * kTbRows * kTbStride;
+    V* bias_lds = reinterpret_cast<V*>(smem + C::kFragBytes);
+    T* tb = reinterpret_cast<T*>(smem + C::kFragBytes + C::kBiasBytes);
 
     Frags<Pol, IN, kLds> fr{frag_lds, params, out, po};
-    if constexpr (kLds) {
-        // the span's tables, prepared by k_mlp_frags, copied 16 bytes per lane
-        const uint4* src = reinterpret_cast<const uint4*>(frags + (int64_t)span * frag_stride);
-        uint4* dst = reinterpret_cast<uint4*>(frag_lds);
-        constexpr int kVec = (int)(Sh::ALL_FRAGS * sizeof(typename Pol::FE) / 16);
-        static_assert(Sh::ALL_FRAGS * sizeof(typename Pol::FE) % 16 == 0, "tables are whole 16-byte vectors");
-        for (int t = threadIdx.x; t < kVec; t += blockDim.x) dst[t] = src[t];
-        for (int t = threadIdx.x; t < po.P; t += blockDim.x) wacc[t] = G(0);
-    }
+    if constexpr (kLds) fill_all_tables<Pol, IN>(frag_lds, params, out, po);
+    for (int t = threadIdx.x; t < 128; t += blockDim.x)
+        bias_lds[t] = (V)Pol::bias(params[t < 64 ? po.b1 + t : po.b2 + t - 64]);
     __syncthreads();
-    V b1[16], b2[16], b3[4];
-    load_biases<Pol>(params, po, out, b1, b2, b3);
+    const LdsBias<Pol> bias{bias_lds};
     const int lane = threadIdx.x & 63, j = lane & 15, kb = lane >> 4;
+    const int wave = threadIdx.x >> 6;
 
-    Acc w3[4], w2[4][4], w1[4][Sh::MF];
+    // Owned gradient blocks: dW3 column tile `wave` (wave < 4); dW2 blocks
+    // (mo2, nt2 + b); dW1 blocks wave + NW b of the (mo, nf) list.  The owner of a
+    // row tile's first block also sums its gradient rows: db3 (wave 0), db2 (nt2 = 0),
+    // db1 (nf = 0).
+    const bool own3 = wave < 4;
+    const int mo2 = (wave * C::B2) >> 2, nt2 = (wave * C::B2) & 3;
+    Acc w3 = Pol::zero(), w2[C::B2], w1[C::B1];
+    V s3 = V(0), s2 = V(0), s1[C::B1];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        w3[a] = Pol::zero();
+    for (int b = 0; b < C::B2; ++b) w2[b] = Pol::zero();
 #pragma unroll
-        for (int b = 0; b < 4; ++b) w2[a][b] = Pol::zero();
-#pragma unroll
-        for (int b = 0; b < Sh::MF; ++b) w1[a][b] = Pol::zero();
+    for (int b = 0; b < C::B1; ++b) {
+        w1[b] = Pol::zero();
+        s1[b] = V(0);
     }
-    V sb1[16], sb2[16], sb3[Sh::NO];
-#pragma unroll
-    for (int idx = 0; idx < 16; ++idx) sb1[idx] = sb2[idx] = V(0);
-#pragma unroll
-    for (int idx = 0; idx < Sh::NO; ++idx) sb3[idx] = V(0);
 
     const int n = sp.n;
     const int tps = (n + 15) / 16;
     const int ntiles = tps * sp.segs;
-    const int stride = (sp.block1 - sp.block0) * kWaves;
-    // the inputs of the wavefront's next tile are loaded while it computes this one
+    // the span's tiles in contiguous, near-equal ranges per workgroup
+    const int nblk = sp.block1 - sp.block0, bi = (int)blockIdx.x - sp.block0;
+    const int t0 = (int)((int64_t)ntiles * bi / nblk), t1 = (int)((int64_t)ntiles * (bi + 1) / nblk);
     auto load_tile = [&](int tile, V (&fv)[Sh::NI], V (&go)[Sh::NO]) {
         const int seg = tile / tps;
         const int q = (tile - seg * tps) * 16 + j;
-        const bool ok = tile < ntiles && q < n;
+        const bool ok = tile < t1 && q < n;
         const V* __restrict__ feat = static_cast<const V*>(sp.feat) + (int64_t)seg * sp.feat_seg;
         const V* __restrict__ d_out = static_cast<const V*>(sp.d_out) + (int64_t)seg * sp.out_seg;
         load_features<Pol, IN>(feat, sp.fv, q, ok, fv);
@@ -526,214 +636,213 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_backward(MlpBatch batch, int 
             go[idx] = (ok && o < out) ? d_out[(int64_t)q * out + o] : V(0);
         }
     };
-    int tile = ((int)blockIdx.x - sp.block0) * kWaves + (int)(threadIdx.x >> 6);
     V next_f[Sh::NI], next_g[Sh::NO];
-    load_tile(tile, next_f, next_g);
-    for (; tile < ntiles; tile += stride) {
-        const int seg = tile / tps;
-        const int q = (tile - seg * tps) * 16 + j;
-        const bool valid = q < n;
-        V* __restrict__ d_feat = static_cast<V*>(sp.d_feat) + (int64_t)seg * sp.feat_seg;
-        V fv[Sh::NI];
-        // upstream gradient of the fused heads, scaled on load
-        V g3[Sh::NO];
+    load_tile(t0 + wave, next_f, next_g);
+    wait_vmem();
+    T* col = tb + 16 * wave + j;  // this lane's staging column
+    for (int base = t0; base < t1; base += NW) {  // uniform over the workgroup
+        const int tile = base + wave;
+        const bool active = tile < t1;
+        // operand groups that hold queries of active tiles (the last iteration of a
+        // range may have fewer than NW)
+        const int ng = (16 * min(NW, t1 - base) + St::QG - 1) / St::QG;
+        V fv[Sh::NI], g3[Sh::NO], h1[16], h2[16], g2[16], g1[16];
 #pragma unroll
         for (int i = 0; i < Sh::NI; ++i) fv[i] = next_f[i];
+        // upstream gradient of the fused heads, scaled on load
 #pragma unroll
-        for (int idx = 0; idx < Sh::NO; ++idx) {
-            g3[idx] = next_g[idx] * in_scale;
-            sb3[idx] += g3[idx];
-        }
-        load_tile(tile + stride, next_f, next_g);
-        V h1[16], h2[16];
-        trunk_forward<Pol, IN>(fr, fv, b1, b2, h1, h2);
-        // dH2^T = W3^T G3^T, masked by ReLU'(z2)
-        Acc a[4];
+        for (int idx = 0; idx < Sh::NO; ++idx) g3[idx] = next_g[idx] * in_scale;
+        if (active) {
+            const int seg = tile / tps;
+            const int q = (tile - seg * tps) * 16 + j;
+            trunk_forward<Pol, IN>(fr, fv, bias, h1, h2);
+            // prefetch after the first products, so that they wait on no load of this iteration
+            load_tile(tile + NW, next_f, next_g);
+            // dH2^T = W3^T G3^T, masked by ReLU'(z2)
+            Acc a[4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::zero();
+            for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::zero();
 #pragma unroll
-        for (int c = 0; c < Sh::NCO; ++c) {
-            const typename Pol::Op b = Pol::pack(&g3[c * Sh::E]);
+            for (int c = 0; c < Sh::NCO; ++c) {
+                const typename Pol::Op b = Pol::pack(&g3[c * Sh::E]);
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::mma(fr.get(Sh::OFF_B3, mt * Sh::NCO + c), b, a[mt]);
-        }
-        V g2[16];
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int idx = mt * 4 + r;
-                g2[idx] = h2[idx] > V(0) ? (V)Pol::get(a[mt], r) : V(0);
-                sb2[idx] += g2[idx];
+                for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::mma(fr.get(kB3, mt, c), b, a[mt]);
             }
-        // dH1^T = W2^T G2^T, masked by ReLU'(z1)
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::zero();
+            for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-        for (int c = 0; c < Sh::NCH; ++c) {
-            const typename Pol::Op b = Pol::pack(&g2[c * Sh::E]);
+                for (int r = 0; r < 4; ++r) g2[mt * 4 + r] = h2[mt * 4 + r] > V(0) ? (V)Pol::get(a[mt], r) : V(0);
+            // dH1^T = W2^T G2^T, masked by ReLU'(z1)
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::mma(fr.get(Sh::OFF_B2, mt * Sh::NCH + c), b, a[mt]);
-        }
-        V g1[16];
+            for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::zero();
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+            for (int c = 0; c < Sh::NCH; ++c) {
+                const typename Pol::Op b = Pol::pack(&g2[c * Sh::E]);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int idx = mt * 4 + r;
-                g1[idx] = h1[idx] > V(0) ? (V)Pol::get(a[mt], r) : V(0);
-                sb1[idx] += g1[idx];
+                for (int mt = 0; mt < 4; ++mt) a[mt] = Pol::mma(fr.get(kB2, mt, c), b, a[mt]);
             }
-        // dF^T = W1^T G1^T
-        Acc af[Sh::MF];
 #pragma unroll
-        for (int mf = 0; mf < Sh::MF; ++mf) af[mf] = Pol::zero();
+            for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-        for (int c = 0; c < Sh::NCH; ++c) {
-            const typename Pol::Op b = Pol::pack(&g1[c * Sh::E]);
+                for (int r = 0; r < 4; ++r) g1[mt * 4 + r] = h1[mt * 4 + r] > V(0) ? (V)Pol::get(a[mt], r) : V(0);
+            // dF^T = W1^T G1^T
+            Acc af[Sh::MF];
 #pragma unroll
-            for (int mf = 0; mf < Sh::MF; ++mf) af[mf] = Pol::mma(fr.get(Sh::OFF_B1, mf * Sh::NCH + c), b, af[mf]);
+            for (int mf = 0; mf < Sh::MF; ++mf) af[mf] = Pol::zero();
+#pragma unroll
+            for (int c = 0; c < Sh::NCH; ++c) {
+                const typename Pol::Op b = Pol::pack(&g1[c * Sh::E]);
+#pragma unroll
+                for (int mf = 0; mf < Sh::MF; ++mf)
+                    af[mf] = Pol::mma(fr.get(kB1, mf, c), b, af[mf]);
+            }
+            if (q < n) {
+                V* __restrict__ d_feat = static_cast<V*>(sp.d_feat) + (int64_t)seg * sp.feat_seg;
+#pragma unroll
+                for (int mf = 0; mf < Sh::MF; ++mf)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int f = 16 * mf + 4 * kb + r;
+                        if (f < IN) d_feat[sp.fv.at(q, f)] = (V)Pol::get(af[mf], r) * feat_scale;
+                    }
+            }
+        } else {
+            // a tile past the range stages zeros (its gradients are zero)
+#pragma unroll
+            for (int idx = 0; idx < 16; ++idx) h1[idx] = h2[idx] = g1[idx] = g2[idx] = V(0);
         }
-        if (valid) {
-#pragma unroll
-            for (int mf = 0; mf < Sh::MF; ++mf)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int f = 16 * mf + 4 * kb + r;
-                    if (f < IN) d_feat[sp.fv.at(q, f)] = (V)Pol::get(af[mf], r) * feat_scale;
-                }
-        }
-        // Weight gradients: stage G^T and H^T rows through this wavefront's LDS buffer.
-        // Stage 1: G3^T rows 0..15, H2^T rows 16..79 -> dW3.
+        // Stage 1: G3^T, H2^T, G1^T, F^T -> dW3, dW1, db3, db1.
+        __syncthreads();  // the previous iteration's dW2 reads are done
 #pragma unroll
         for (int idx = 0; idx < Sh::NO; ++idx) {
             const int o = kb * Sh::NO + idx;
-            if (o < 16) tb[o * kTbStride + j] = g3[idx];
+            if (o < 16) St::put(col + (C::R_G3 + o) * S, g3[idx]);
         }
-#pragma unroll
-        for (int idx = 0; idx < 16; ++idx) tb[(16 + hid(idx, kb)) * kTbStride + j] = h2[idx];
-        __builtin_amdgcn_wave_barrier();
-        {
-            const WOp<Pol> ga = wload<Pol>(tb, 0);
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) wmma<Pol>(w3[nt], ga, wload<Pol>(tb, 16 + 16 * nt));
-        }
-        __builtin_amdgcn_wave_barrier();
-        // Stage 2: G2^T rows 0..63, H1^T rows 64..127 -> dW2.
 #pragma unroll
         for (int idx = 0; idx < 16; ++idx) {
-            tb[hid(idx, kb) * kTbStride + j] = g2[idx];
-            tb[(64 + hid(idx, kb)) * kTbStride + j] = h1[idx];
+            St::put(col + (C::R_H2 + hid(idx, kb)) * S, h2[idx]);
+            St::put(col + (C::R_G1 + hid(idx, kb)) * S, g1[idx]);
         }
-        __builtin_amdgcn_wave_barrier();
-        {
-            WOp<Pol> hb[4];
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) hb[nt] = wload<Pol>(tb, 64 + 16 * nt);
-#pragma unroll
-            for (int mo = 0; mo < 4; ++mo) {
-                const WOp<Pol> ga = wload<Pol>(tb, 16 * mo);
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) wmma<Pol>(w2[mo][nt], ga, hb[nt]);
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        // Stage 3: G1^T rows 0..63, F^T rows 64..(64 + 16 MF) -> dW1.
-#pragma unroll
-        for (int idx = 0; idx < 16; ++idx) tb[hid(idx, kb) * kTbStride + j] = g1[idx];
 #pragma unroll
         for (int idx = 0; idx < Sh::NI; ++idx) {
             const int k = kb * Sh::NI + idx;
-            if (k < 16 * Sh::MF) tb[(64 + k) * kTbStride + j] = fv[idx];
+            if (k < 16 * Sh::MF) St::put(col + (C::R_F + k) * S, fv[idx]);
         }
-        __builtin_amdgcn_wave_barrier();
-        {
-            WOp<Pol> fb[Sh::MF];
+        __syncthreads();
+        // The contractions run over the operand groups that hold active queries: all
+        // NG of them (straight-line code) except in a range's last, partial iteration.
+        // Each contraction first reads all its operand groups, then issues its products,
+        // so that the LDS latency is paid once per block rather than once per group.
+        auto block = [&](auto full, Acc& acc, V& rsum, bool with_sum, const T* ra, const T* rb) {
+            constexpr bool kFull = decltype(full)::value;
+            typename St::Grp ga[C::NG], gb[C::NG];
 #pragma unroll
-            for (int nf = 0; nf < Sh::MF; ++nf) fb[nf] = wload<Pol>(tb, 64 + 16 * nf);
+            for (int m = 0; m < C::NG; ++m)
+                if (kFull || m < ng) {
+                    ga[m] = St::load(ra, m);
+                    gb[m] = St::load(rb, m);
+                }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int mo = 0; mo < 4; ++mo) {
-                const WOp<Pol> ga = wload<Pol>(tb, 16 * mo);
+            for (int m = 0; m < C::NG; ++m)
+                if (kFull || m < ng) St::mma(acc, ga[m], gb[m]);
+            if (with_sum) {
 #pragma unroll
-                for (int nf = 0; nf < Sh::MF; ++nf) wmma<Pol>(w1[mo][nf], ga, fb[nf]);
+                for (int m = 0; m < C::NG; ++m)
+                    if (kFull || m < ng) rsum += St::sum(ga[m]);
             }
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-
-    // Reduce the bias sums over the 16 query lanes of each lane group.
+        };
+        auto stage1 = [&](auto full) {
+            if (own3) block(full, w3, s3, wave == 0, tb + (C::R_G3 + j) * S, tb + (C::R_H2 + 16 * wave + j) * S);
 #pragma unroll
-    for (int s = 1; s < 16; s <<= 1) {
+            for (int b = 0; b < C::B1; ++b) {
+                const int id = wave + NW * b;
+                if (id < 4 * Sh::MF)
+                    block(full, w1[b], s1[b], id % Sh::MF == 0, tb + (C::R_G1 + 16 * (id / Sh::MF) + j) * S,
+                          tb + (C::R_F + 16 * (id % Sh::MF) + j) * S);
+            }
+        };
+        auto stage2 = [&](auto full) {
+            constexpr bool kFull = decltype(full)::value;
+            const T* ra = tb + (C::R_G2 + 16 * mo2 + j) * S;
+            typename St::Grp ga[C::NG], gb[C::NG][C::B2];
+#pragma unroll
+            for (int m = 0; m < C::NG; ++m)
+                if (kFull || m < ng) {
+                    ga[m] = St::load(ra, m);
+#pragma unroll
+                    for (int b = 0; b < C::B2; ++b) gb[m][b] = St::load(tb + (C::R_H1 + 16 * (nt2 + b) + j) * S, m);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int m = 0; m < C::NG; ++m)
+                if (kFull || m < ng) {
+#pragma unroll
+                    for (int b = 0; b < C::B2; ++b) St::mma(w2[b], ga[m], gb[m][b]);
+                }
+            if (nt2 == 0) {
+#pragma unroll
+                for (int m = 0; m < C::NG; ++m)
+                    if (kFull || m < ng) s2 += St::sum(ga[m]);
+            }
+        };
+        if (ng == C::NG) stage1(std::true_type{});
+        else stage1(std::false_type{});
+        __syncthreads();
+        // Stage 2: G2^T, H1^T -> dW2, db2.
 #pragma unroll
         for (int idx = 0; idx < 16; ++idx) {
-            sb1[idx] += __shfl_xor(sb1[idx], s, 64);
-            sb2[idx] += __shfl_xor(sb2[idx], s, 64);
+            St::put(col + (C::R_G2 + hid(idx, kb)) * S, g2[idx]);
+            St::put(col + (C::R_H1 + hid(idx, kb)) * S, h1[idx]);
         }
-#pragma unroll
-        for (int idx = 0; idx < Sh::NO; ++idx) sb3[idx] += __shfl_xor(sb3[idx], s, 64);
+        __syncthreads();
+        if (ng == C::NG) stage2(std::true_type{});
+        else stage2(std::false_type{});
     }
 
-    // Emit the wavefront partial gradients.  FP32/BF16: the parameters fall into four
-    // blocks (row tiles mo of W1 and W2, column tiles nt of W3, quarters of b1 and b2;
-    // b3 joins block 0), and in round r wavefront w adds its block (w + r) mod 4 to
-    // the block accumulator in LDS with plain read-modify-writes.  The four
-    // wavefronts work on disjoint blocks at once, and every parameter receives the
-    // wavefronts' sums in a fixed order.  FP64: each wavefront writes its own row.
-    static_assert(!kLds || kWaves == 4, "one parameter block per wavefront");
-    const int wave = threadIdx.x >> 6;
-    G* dst = kLds ? wacc : partial + (size_t)(blockIdx.x * kWaves + wave) * po.P;
-    auto emit = [&](int p, G v) {
-        if constexpr (kLds) dst[p] += v;
-        else dst[p] = v;
+    // Bias sums: lane (j, kb) holds row j's sum over its K slots; add the four lane
+    // groups in a fixed order.
+    auto row_total = [&](V v) {
+        v += __shfl_xor(v, 16, 64);
+        return v + __shfl_xor(v, 32, 64);
     };
-    for (int round = 0; round < (kLds ? kWaves : 1); ++round) {
-        const int blk = (wave + round) & 3;
-        auto mine = [&](int b) { return !kLds || b == blk; };
+    s3 = row_total(s3);
+    s2 = row_total(s2);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-            if (mine(nt)) {
+    for (int b = 0; b < C::B1; ++b) s1[b] = row_total(s1[b]);
+    // Every parameter of the block's partial row is written exactly once.
+    G* row = partial + (size_t)blockIdx.x * po.P;
+    if (kb == 0) {
+        if (wave == 0 && j < out) row[po.b3 + j] = (G)s3;
+        if (nt2 == 0) row[po.b2 + 16 * mo2 + j] = (G)s2;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int o = 4 * kb + r;
-                    if (o < out) emit(po.W3 + o * HID + 16 * nt + j, (G)Pol::get(w3[nt], r));
-                }
-            }
+        for (int b = 0; b < C::B1; ++b) {
+            const int id = wave + NW * b;
+            if (id < 4 * Sh::MF && id % Sh::MF == 0) row[po.b1 + 16 * (id / Sh::MF) + j] = (G)s1[b];
+        }
+    }
+    if (own3) {
 #pragma unroll
-        for (int mo = 0; mo < 4; ++mo)
-            if (mine(mo)) {
+        for (int r = 0; r < 4; ++r) {
+            const int o = 4 * kb + r;
+            if (o < out) row[po.W3 + o * HID + 16 * wave + j] = (G)Pol::get(w3, r);
+        }
+    }
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
+    for (int b = 0; b < C::B2; ++b)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        emit(po.W2 + (16 * mo + 4 * kb + r) * HID + 16 * nt + j, (G)Pol::get(w2[mo][nt], r));
+        for (int r = 0; r < 4; ++r)
+            row[po.W2 + (16 * mo2 + 4 * kb + r) * HID + 16 * (nt2 + b) + j] = (G)Pol::get(w2[b], r);
 #pragma unroll
-                for (int nf = 0; nf < Sh::MF; ++nf)
+    for (int b = 0; b < C::B1; ++b) {
+        const int id = wave + NW * b;
+        if (id < 4 * Sh::MF) {
+            const int mo = id / Sh::MF, f = 16 * (id % Sh::MF) + j;
+            if (f < IN) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int f = 16 * nf + j;
-                        if (f < IN) emit(po.W1 + (16 * mo + 4 * kb + r) * IN + f, (G)Pol::get(w1[mo][nf], r));
-                    }
-            }
-        if (j == 0) {
-#pragma unroll
-            for (int idx = 0; idx < 16; ++idx)
-                if (mine(idx >> 2)) {
-                    emit(po.b1 + hid(idx, kb), (G)sb1[idx]);
-                    emit(po.b2 + hid(idx, kb), (G)sb2[idx]);
-                }
-            if (mine(0)) {
-#pragma unroll
-                for (int idx = 0; idx < Sh::NO; ++idx) {
-                    const int o = kb * Sh::NO + idx;
-                    if (o < out) emit(po.b3 + o, (G)sb3[idx]);
-                }
+                for (int r = 0; r < 4; ++r) row[po.W1 + (16 * mo + 4 * kb + r) * IN + f] = (G)Pol::get(w1[b], r);
             }
         }
-        if constexpr (kLds) __syncthreads();
-    }
-    if constexpr (kLds) {
-        G* row = partial + (size_t)blockIdx.x * po.P;
-        for (int t = threadIdx.x; t < po.P; t += blockDim.x) row[t] = wacc[t];
     }
 }
 
@@ -769,8 +878,9 @@ __global__ __launch_bounds__(kRedParams * kRedGroups) void k_mlp_reduce(MlpBatch
 }
 
 // ------------------------------------------------------------------ host ----
-// Persistent grids: the forward kernel fits several blocks per CU, the backward
-// kernel's LDS (fragment tables, gradient accumulator, transpose buffers) one.
+// Persistent grids: the forward kernel fits several blocks per CU; the backward
+// kernel one of 8 wavefronts (two per SIMD: its registers; for FP32 also its LDS,
+// the fragment tables and a 128-query staging buffer).
 constexpr int kMlpFwdMaxBlocks = 1024;
 constexpr int kMlpBwdMaxBlocks = 256;
 constexpr int kMlpF64MaxBlocks = 64;   // the FP64 check path spills to scratch: keep its grid small
@@ -784,19 +894,7 @@ static int mlp_blocks(int n, int cap) {
 template <class Pol, int IN>
 static size_t lds_forward(int out) {
     if (std::is_same<Pol, PolF64>::value) return 0;
-    return ((size_t)Shape<Pol, IN>::FWD_FRAGS * sizeof(typename Pol::FE) + 15) / 16 * 16;
-}
-
-template <class Pol, int IN>
-static size_t lds_backward(int out) {
-    const ParamOff po(IN, out);
-    size_t s = 0;
-    if (!std::is_same<Pol, PolF64>::value) {
-        s += ((size_t)Shape<Pol, IN>::ALL_FRAGS * sizeof(typename Pol::FE) + 15) / 16 * 16;
-        s += ((size_t)po.P * sizeof(typename Pol::G) + 15) / 16 * 16;
-    }
-    s += (size_t)kWaves * kTbRows * kTbStride * sizeof(typename Pol::V);
-    return s;
+    return ((size_t)Tab<Pol, IN>::FWD * sizeof(typename Pol::FE) + 15) / 16 * 16;
 }
 
 size_t mlp_workspace_bytes(h4d_dtype dt, int in, int out, int n) {
@@ -820,51 +918,25 @@ static size_t align_up(size_t b) { return (b + 255) / 256 * 256; }
 template <class Pol>
 static size_t partial_rows_bytes(int in, int out, int blocks) {
     const ParamOff po(in, out);
-    return (size_t)blocks * (std::is_same<Pol, PolF64>::value ? kWaves : 1) * po.P * sizeof(typename Pol::G);
-}
-
-template <class Pol, int IN>
-static size_t frag_table_bytes() {
-    return align_up((size_t)Shape<Pol, IN>::ALL_FRAGS * sizeof(typename Pol::FE));
-}
-
-template <class Pol>
-static size_t frag_table_bytes_for(int in) {
-    switch (in) {
-        case 8: return frag_table_bytes<Pol, 8>();
-        case 16: return frag_table_bytes<Pol, 16>();
-        case 32: return frag_table_bytes<Pol, 32>();
-        default: return frag_table_bytes<Pol, 64>();
-    }
+    return (size_t)blocks * po.P * sizeof(typename Pol::G);
 }
 
 template <class Pol, int IN>
 static hipError_t backward_t(const MlpBatch& b, int blocks, int out, double in_scale, double feat_scale,
                              double param_scale, void* ws, hipStream_t s) {
-    const size_t lds = lds_backward<Pol, IN>(out);
+    const size_t lds = Bwd<Pol, IN>::kLdsBytes;
     auto kern = k_mlp_backward<Pol, IN>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     using V = typename Pol::V;
     using G = typename Pol::G;
-    using FE = typename Pol::FE;
-    using Sh = Shape<Pol, IN>;
-    // workspace: [per-block partial rows | per-span fragment tables (FP32/BF16)]
-    FE* frags = nullptr;
-    const int64_t stride = (int64_t)(frag_table_bytes<Pol, IN>() / sizeof(FE));
-    if constexpr (!std::is_same<Pol, PolF64>::value) {
-        frags = reinterpret_cast<FE*>(static_cast<char*>(ws) + align_up(partial_rows_bytes<Pol>(IN, out, blocks)));
-        hipLaunchKernelGGL((k_mlp_frags<Pol, IN>), dim3((Sh::ALL_FRAGS + 255) / 256, b.count), dim3(256), 0, s, b,
-                           out, frags, stride);
-    }
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kMlpBlock), lds, s, b, out, (V)in_scale, (V)feat_scale,
-                       static_cast<G*>(ws), frags, stride);
+    // workspace: the per-block partial rows
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * Bwd<Pol, IN>::NW), lds, s, b, out, (V)in_scale,
+                       (V)feat_scale, static_cast<G*>(ws));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const ParamOff po(IN, out);
-    const int rows_per_block = std::is_same<Pol, PolF64>::value ? kWaves : 1;
     hipLaunchKernelGGL(k_mlp_reduce<G>, dim3((po.P + kRedParams - 1) / kRedParams, b.count),
-                       dim3(kRedParams * kRedGroups), 0, s, b, static_cast<const G*>(ws), rows_per_block, po.P,
-                       (G)param_scale);
+                       dim3(kRedParams * kRedGroups), 0, s, b, static_cast<const G*>(ws), 1, po.P, (G)param_scale);
     return hipGetLastError();
 }
 
@@ -898,11 +970,11 @@ int mlp_blocks_for(h4d_dtype dt, bool backward, int64_t queries) {
     return mlp_blocks((int)(queries < 2147483647 ? queries : 2147483647), cap);
 }
 
-size_t mlp_partial_bytes(h4d_dtype dt, int in, int out, int blocks, int spans) {
+size_t mlp_partial_bytes(h4d_dtype dt, int in, int out, int blocks, int) {
     switch (dt) {
-        case H4D_F32: return align_up(partial_rows_bytes<PolF32>(in, out, blocks)) + spans * frag_table_bytes_for<PolF32>(in);
-        case H4D_BF16: return align_up(partial_rows_bytes<PolBF16>(in, out, blocks)) + spans * frag_table_bytes_for<PolBF16>(in);
-        default: return partial_rows_bytes<PolF64>(in, out, blocks);
+        case H4D_F32: return align_up(partial_rows_bytes<PolF32>(in, out, blocks));
+        case H4D_BF16: return align_up(partial_rows_bytes<PolBF16>(in, out, blocks));
+        default: return align_up(partial_rows_bytes<PolF64>(in, out, blocks));
     }
 }
 
