@@ -494,7 +494,6 @@ struct Stage<PolF32> {
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[e], b.v[e], acc, 0, 0, 0);
     }
-    __device__ static float sum(const Grp& a) { return (a.v[0] + a.v[1]) + (a.v[2] + a.v[3]); }
 };
 
 template <>
@@ -511,12 +510,6 @@ struct Stage<PolBF16> {
     }
     __device__ static void mma(floatx4& acc, const Grp& a, const Grp& b) {
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
-    }
-    __device__ static float sum(const Grp& a) {
-        float t[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) t[e] = (float)a.v[2 * e] + (float)a.v[2 * e + 1];
-        return (t[0] + t[1]) + (t[2] + t[3]);
     }
 };
 
@@ -536,7 +529,77 @@ struct Stage<PolF64> {
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc = PolF64::mma(a.v[e], b.v[e], acc);
     }
-    __device__ static double sum(const Grp& a) { return (a.v[0] + a.v[1]) + (a.v[2] + a.v[3]); }
+};
+
+// BF16 staging through the matrix pipe.  A product with a 0/1 selection matrix
+// turns one chunk of chain values (lane (q, kb) holding, at query q, the rows
+// hid(8 c + e, kb) or kb stride + 8 c + e, e < 8) into one 16-row tile of the staged
+// layout: lane (n, kb) then holds row n at queries 4 kb .. 4 kb + 3, which it stores
+// with one 8-byte write.  Each output is one product with 1, so it is exact.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ bf16x8 select_at(int target) {
+    bf16x8 r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = e == target ? (__bf16)1.0f : (__bf16)0.0f;
+    return r;
+}
+// rows hid(8 c + e, kb) of chunk c = nt / 2 onto tile nt (half = nt % 2)
+__device__ __forceinline__ bf16x8 select_hid(int half) {
+    const int lane = threadIdx.x & 63, n = lane & 15, kb = lane >> 4;
+    const int d = n - 4 * kb;
+    return select_at(d >= 0 && d < 4 ? 4 * half + d : -1);
+}
+// rows kb stride + 8 c + e of chunk c onto tile nt
+__device__ __forceinline__ bf16x8 select_lin(int stride, int c, int nt) {
+    const int lane = threadIdx.x & 63, n = lane & 15, kb = lane >> 4;
+    const int e = 16 * nt + n - kb * stride - 8 * c;
+    return select_at(e >= 0 && e < 8 ? e : -1);
+}
+__device__ __forceinline__ floatx4 select_mma(const bf16x8& a, const bf16x8& sel, floatx4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, sel, acc, 0, 0, 0);
+}
+// stores the tile (row n at this lane's four queries) into staging rows row0 ..
+__device__ __forceinline__ void put_tile(uint16_t* tb, int S, int row0, int wave, const floatx4& d) {
+    const int lane = threadIdx.x & 63, n = lane & 15, kb = lane >> 4;
+    const bf16x2 lo = {(__bf16)d[0], (__bf16)d[1]}, hi = {(__bf16)d[2], (__bf16)d[3]};
+    *reinterpret_cast<uint2*>(tb + (row0 + n) * S + 16 * wave + 4 * kb) =
+        uint2{__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi)};
+}
+
+// Sums over queries of the rows of a staged 16-row block (the bias gradients).
+// FP32 / FP64: lane (j, kb) adds up row j over its K slots; the four lane groups are
+// added at the end.  BF16: one more product per operand group, with a vector of
+// ones (the matrix pipe is idle there); lane (j, kb) then holds rows 4 kb + r.
+template <class Pol>
+struct RowSum {
+    typename Pol::V s = 0;
+    __device__ void add(const typename Stage<Pol>::Grp& g) { s += (g.v[0] + g.v[1]) + (g.v[2] + g.v[3]); }
+    template <class F>
+    __device__ void emit(F&& f) {
+        typename Pol::V t = s + __shfl_xor(s, 16, 64);
+        t += __shfl_xor(t, 32, 64);
+        if ((threadIdx.x & 63) < 16) f(threadIdx.x & 15, t);
+    }
+};
+
+template <>
+struct RowSum<PolBF16> {
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    __device__ void add(const Stage<PolBF16>::Grp& g) {
+        bf16x8 ones;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g.v, ones, acc, 0, 0, 0);
+    }
+    template <class F>
+    __device__ void emit(F&& f) {
+        const int lane = threadIdx.x & 63;
+        if ((lane & 15) == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) f(4 * (lane >> 4) + r, acc[r]);
+        }
+    }
 };
 
 constexpr size_t kLdsBudget = 160 * 1024;
@@ -608,14 +671,11 @@ __global__ __launch_bounds__((bwd_threads<Pol, IN>())) void k_mlp_backward(MlpBa
     const bool own3 = wave < 4;
     const int mo2 = (wave * C::B2) >> 2, nt2 = (wave * C::B2) & 3;
     Acc w3 = Pol::zero(), w2[C::B2], w1[C::B1];
-    V s3 = V(0), s2 = V(0), s1[C::B1];
+    RowSum<Pol> s3, s2, s1[C::B1];
 #pragma unroll
     for (int b = 0; b < C::B2; ++b) w2[b] = Pol::zero();
 #pragma unroll
-    for (int b = 0; b < C::B1; ++b) {
-        w1[b] = Pol::zero();
-        s1[b] = V(0);
-    }
+    for (int b = 0; b < C::B1; ++b) w1[b] = Pol::zero();
 
     const int n = sp.n;
     const int tps = (n + 15) / 16;
@@ -713,27 +773,45 @@ __global__ __launch_bounds__((bwd_threads<Pol, IN>())) void k_mlp_backward(MlpBa
         }
         // Stage 1: G3^T, H2^T, G1^T, F^T -> dW3, dW1, db3, db1.
         __syncthreads();  // the previous iteration's dW2 reads are done
+        if constexpr (std::is_same<Pol, PolBF16>::value) {
+            const floatx4 z = Pol::zero();
+            put_tile(tb, S, C::R_G3, wave, select_mma(Pol::pack(&g3[0]), select_lin(Sh::NO, 0, 0), z));
 #pragma unroll
-        for (int idx = 0; idx < Sh::NO; ++idx) {
-            const int o = kb * Sh::NO + idx;
-            if (o < 16) St::put(col + (C::R_G3 + o) * S, g3[idx]);
-        }
+            for (int nt = 0; nt < 4; ++nt) {
+                const bf16x8 sel = select_hid(nt & 1);
+                put_tile(tb, S, C::R_H2 + 16 * nt, wave, select_mma(Pol::pack(&h2[8 * (nt >> 1)]), sel, z));
+                put_tile(tb, S, C::R_G1 + 16 * nt, wave, select_mma(Pol::pack(&g1[8 * (nt >> 1)]), sel, z));
+            }
 #pragma unroll
-        for (int idx = 0; idx < 16; ++idx) {
-            St::put(col + (C::R_H2 + hid(idx, kb)) * S, h2[idx]);
-            St::put(col + (C::R_G1 + hid(idx, kb)) * S, g1[idx]);
-        }
+            for (int nf = 0; nf < Sh::MF; ++nf) {
+                floatx4 d = z;
 #pragma unroll
-        for (int idx = 0; idx < Sh::NI; ++idx) {
-            const int k = kb * Sh::NI + idx;
-            if (k < 16 * Sh::MF) St::put(col + (C::R_F + k) * S, fv[idx]);
+                for (int c = 0; c < Sh::NC1; ++c) d = select_mma(Pol::pack(&fv[8 * c]), select_lin(Sh::NI, c, nf), d);
+                put_tile(tb, S, C::R_F + 16 * nf, wave, d);
+            }
+        } else {
+#pragma unroll
+            for (int idx = 0; idx < Sh::NO; ++idx) {
+                const int o = kb * Sh::NO + idx;
+                if (o < 16) St::put(col + (C::R_G3 + o) * S, g3[idx]);
+            }
+#pragma unroll
+            for (int idx = 0; idx < 16; ++idx) {
+                St::put(col + (C::R_H2 + hid(idx, kb)) * S, h2[idx]);
+                St::put(col + (C::R_G1 + hid(idx, kb)) * S, g1[idx]);
+            }
+#pragma unroll
+            for (int idx = 0; idx < Sh::NI; ++idx) {
+                const int k = kb * Sh::NI + idx;
+                if (k < 16 * Sh::MF) St::put(col + (C::R_F + k) * S, fv[idx]);
+            }
         }
         __syncthreads();
         // The contractions run over the operand groups that hold active queries: all
         // NG of them (straight-line code) except in a range's last, partial iteration.
         // Each contraction first reads all its operand groups, then issues its products,
         // so that the LDS latency is paid once per block rather than once per group.
-        auto block = [&](auto full, Acc& acc, V& rsum, bool with_sum, const T* ra, const T* rb) {
+        auto block = [&](auto full, Acc& acc, RowSum<Pol>& rsum, bool with_sum, const T* ra, const T* rb) {
             constexpr bool kFull = decltype(full)::value;
             typename St::Grp ga[C::NG], gb[C::NG];
 #pragma unroll
@@ -749,7 +827,7 @@ __global__ __launch_bounds__((bwd_threads<Pol, IN>())) void k_mlp_backward(MlpBa
             if (with_sum) {
 #pragma unroll
                 for (int m = 0; m < C::NG; ++m)
-                    if (kFull || m < ng) rsum += St::sum(ga[m]);
+                    if (kFull || m < ng) rsum.add(ga[m]);
             }
         };
         auto stage1 = [&](auto full) {
@@ -783,43 +861,42 @@ __global__ __launch_bounds__((bwd_threads<Pol, IN>())) void k_mlp_backward(MlpBa
             if (nt2 == 0) {
 #pragma unroll
                 for (int m = 0; m < C::NG; ++m)
-                    if (kFull || m < ng) s2 += St::sum(ga[m]);
+                    if (kFull || m < ng) s2.add(ga[m]);
             }
         };
         if (ng == C::NG) stage1(std::true_type{});
         else stage1(std::false_type{});
         __syncthreads();
         // Stage 2: G2^T, H1^T -> dW2, db2.
+        if constexpr (std::is_same<Pol, PolBF16>::value) {
+            const floatx4 z = Pol::zero();
 #pragma unroll
-        for (int idx = 0; idx < 16; ++idx) {
-            St::put(col + (C::R_G2 + hid(idx, kb)) * S, g2[idx]);
-            St::put(col + (C::R_H1 + hid(idx, kb)) * S, h1[idx]);
+            for (int nt = 0; nt < 4; ++nt) {
+                const bf16x8 sel = select_hid(nt & 1);
+                put_tile(tb, S, C::R_G2 + 16 * nt, wave, select_mma(Pol::pack(&g2[8 * (nt >> 1)]), sel, z));
+                put_tile(tb, S, C::R_H1 + 16 * nt, wave, select_mma(Pol::pack(&h1[8 * (nt >> 1)]), sel, z));
+            }
+        } else {
+#pragma unroll
+            for (int idx = 0; idx < 16; ++idx) {
+                St::put(col + (C::R_G2 + hid(idx, kb)) * S, g2[idx]);
+                St::put(col + (C::R_H1 + hid(idx, kb)) * S, h1[idx]);
+            }
         }
         __syncthreads();
         if (ng == C::NG) stage2(std::true_type{});
         else stage2(std::false_type{});
     }
 
-    // Bias sums: lane (j, kb) holds row j's sum over its K slots; add the four lane
-    // groups in a fixed order.
-    auto row_total = [&](V v) {
-        v += __shfl_xor(v, 16, 64);
-        return v + __shfl_xor(v, 32, 64);
-    };
-    s3 = row_total(s3);
-    s2 = row_total(s2);
-#pragma unroll
-    for (int b = 0; b < C::B1; ++b) s1[b] = row_total(s1[b]);
     // Every parameter of the block's partial row is written exactly once.
     G* row = partial + (size_t)blockIdx.x * po.P;
-    if (kb == 0) {
-        if (wave == 0 && j < out) row[po.b3 + j] = (G)s3;
-        if (nt2 == 0) row[po.b2 + 16 * mo2 + j] = (G)s2;
+    if (wave == 0) s3.emit([&](int r, V v) { if (r < out) row[po.b3 + r] = (G)v; });
+    if (nt2 == 0) s2.emit([&](int r, V v) { row[po.b2 + 16 * mo2 + r] = (G)v; });
 #pragma unroll
-        for (int b = 0; b < C::B1; ++b) {
-            const int id = wave + NW * b;
-            if (id < 4 * Sh::MF && id % Sh::MF == 0) row[po.b1 + 16 * (id / Sh::MF) + j] = (G)s1[b];
-        }
+    for (int b = 0; b < C::B1; ++b) {
+        const int id = wave + NW * b;
+        if (id < 4 * Sh::MF && id % Sh::MF == 0)
+            s1[b].emit([&](int r, V v) { row[po.b1 + 16 * (id / Sh::MF) + r] = (G)v; });
     }
     if (own3) {
 #pragma unroll
