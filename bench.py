@@ -425,16 +425,26 @@ def batched_form(torch, _lib, synth, steps: int, warmup: int):
         descs.append(_lib.scene_desc(g, n, s["xyz"], synth.BATCHED_TIMES, s["t"], s["p"], s["feat"], s["delta"],
                                      s["gd"], s["dt"], s["dp"], table_master=s["tm"], params_master=s["pm"]))
     flags = _lib.PLAN_AUTOTUNE | _lib.PLAN_GRAPH | _lib.PLAN_ZERO_GRADS
+
+    def timed(plan):
+        for _ in range(warmup):
+            plan.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.run()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # the same plan in FP32: the FP32 masters are the tables and decoders themselves
+    descs32 = [_lib.scene_desc(s["g"], s["n"], s["xyz"], synth.BATCHED_TIMES, s["tm"], s["pm"], s["feat"],
+                               s["delta"], s["gd"], s["dt"], s["dp"]) for s in keep]
+    plan32 = _lib.BatchedPlan(descs32, m, _lib.F32, 1.0, flags)
+    wall32 = timed(plan32)
+    plan32.destroy()
     plan = _lib.BatchedPlan(descs, m, _lib.BF16, 4096.0, flags)
     info = plan.info()
-    for _ in range(warmup):
-        plan.run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.run()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall = timed(plan)
     q = info.queries
     # the same work as plain per-(scene, timestamp) calls
     ws = {}
@@ -470,7 +480,8 @@ def batched_form(torch, _lib, synth, steps: int, warmup: int):
             "schedule": {"encode_qpt_lpb_grid": [info.encode_qpt, info.encode_lpb, info.encode_grid],
                          "scatter_tiles": info.scatter_tiles},
             "graph": bool(info.graph), "unbatched_value": q * u_steps / u_wall,
-            "unbatched_ms_per_step": u_wall * 1e3 / u_steps}
+            "unbatched_ms_per_step": u_wall * 1e3 / u_steps,
+            "fp32": {"value": q * steps / wall32, "ms_per_step": wall32 * 1e3 / steps}}
 
 
 def form_differences(ref32: dict, path) -> dict:

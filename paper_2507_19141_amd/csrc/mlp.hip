@@ -35,8 +35,6 @@ typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 constexpr int HID = H4D_HIDDEN;
 constexpr int OUTP = H4D_MAX_OUT;
-constexpr int kMlpBlock = 256;
-constexpr int kWaves = kMlpBlock / 64;
 
 __device__ __forceinline__ int hid(int idx, int kb) { return 16 * (idx >> 2) + 4 * kb + (idx & 3); }
 
@@ -238,14 +236,15 @@ struct Frags {
 
 // Builds the LDS table of matrix M: wavefront-strided over its units, each lane
 // gathering its grp E (L2-resident) parameters and storing them together.
-template <class Pol, int IN, int M>
+template <class Pol, int IN, int M, int NW>
 __device__ __forceinline__ void fill_table(typename Pol::FE* lds, const typename Pol::S* __restrict__ params, int out,
                                            const ParamOff& po) {
     using TB = Tab<Pol, IN>;
     using FE = typename Pol::FE;
     constexpr int G = TB::grp(M), GE = G * Pol::E, NCG = TB::nc(M) / G, UNITS = TB::tiles(M) * NCG;
-    const int lane = threadIdx.x & 63, nw = (int)(blockDim.x >> 6);
-    for (int u = (int)(threadIdx.x >> 6); u < UNITS; u += nw) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = (int)(threadIdx.x >> 6); u < UNITS; u += NW) {
         const int mt = u / NCG, c0 = (u % NCG) * G;
         FE v[GE];
 #pragma unroll
@@ -267,21 +266,21 @@ __device__ __forceinline__ void fill_table(typename Pol::FE* lds, const typename
     }
 }
 
-template <class Pol, int IN>
+template <class Pol, int IN, int NW>
 __device__ void fill_forward_tables(typename Pol::FE* lds, const typename Pol::S* __restrict__ params, int out,
                                     const ParamOff& po) {
-    fill_table<Pol, IN, kA1>(lds, params, out, po);
-    fill_table<Pol, IN, kA2>(lds, params, out, po);
-    fill_table<Pol, IN, kA3>(lds, params, out, po);
+    fill_table<Pol, IN, kA1, NW>(lds, params, out, po);
+    fill_table<Pol, IN, kA2, NW>(lds, params, out, po);
+    fill_table<Pol, IN, kA3, NW>(lds, params, out, po);
 }
 
-template <class Pol, int IN>
+template <class Pol, int IN, int NW>
 __device__ void fill_all_tables(typename Pol::FE* lds, const typename Pol::S* __restrict__ params, int out,
                                 const ParamOff& po) {
-    fill_forward_tables<Pol, IN>(lds, params, out, po);
-    fill_table<Pol, IN, kB3>(lds, params, out, po);
-    fill_table<Pol, IN, kB2>(lds, params, out, po);
-    fill_table<Pol, IN, kB1>(lds, params, out, po);
+    fill_forward_tables<Pol, IN, NW>(lds, params, out, po);
+    fill_table<Pol, IN, kB3, NW>(lds, params, out, po);
+    fill_table<Pol, IN, kB2, NW>(lds, params, out, po);
+    fill_table<Pol, IN, kB1, NW>(lds, params, out, po);
 }
 
 __device__ __forceinline__ int span_of_block(const MlpBatch& b) {
@@ -398,13 +397,18 @@ __device__ __forceinline__ void load_biases(const typename Pol::S* __restrict__ 
 }
 
 // ---------------------------------------------------------------- forward ----
-// Four wavefronts per SIMD (128 VGPRs) where the layer chain fits without spilling.
+// Workgroups of 4 wavefronts; four wavefronts per SIMD (128 VGPRs) where the layer
+// chain fits without spilling.  (Workgroups of 16 wavefronts, which build the
+// fragment tables once per CU, measured slower in FP32: 40.4 against 37.5 us.)
+template <class Pol, int IN>
+constexpr int fwd_threads() { return 256; }
 template <class Pol, int IN>
 constexpr int fwd_waves_per_eu() { return (std::is_same<Pol, PolF64>::value || IN > 32) ? 1 : 4; }
 
 template <class Pol, int IN>
-__global__ __launch_bounds__(kMlpBlock) __attribute__((amdgpu_waves_per_eu(fwd_waves_per_eu<Pol, IN>())))
+__global__ __launch_bounds__((fwd_threads<Pol, IN>())) __attribute__((amdgpu_waves_per_eu(fwd_waves_per_eu<Pol, IN>())))
 void k_mlp_forward(MlpBatch batch, int out) {
+    constexpr int kWaves = fwd_threads<Pol, IN>() / 64;
     using Sh = Shape<Pol, IN>;
     using V = typename Pol::V;
     constexpr bool kLds = !std::is_same<Pol, PolF64>::value;
@@ -414,7 +418,7 @@ void k_mlp_forward(MlpBatch batch, int out) {
     const ParamOff po(IN, out);
     Frags<Pol, IN, kLds> fr{reinterpret_cast<const typename Pol::FE*>(smem), params, out, po};
     if constexpr (kLds)  // no staging buffer: the forward keeps its LDS small for occupancy
-        fill_forward_tables<Pol, IN>(reinterpret_cast<typename Pol::FE*>(smem), params, out, po);
+        fill_forward_tables<Pol, IN, kWaves>(reinterpret_cast<typename Pol::FE*>(smem), params, out, po);
     __syncthreads();
     V b1[16], b2[16], b3[4];
     load_biases<Pol>(params, po, out, b1, b2, b3);
@@ -656,7 +660,7 @@ __global__ __launch_bounds__((bwd_threads<Pol, IN>())) void k_mlp_backward(MlpBa
     T* tb = reinterpret_cast<T*>(smem + C::kFragBytes + C::kBiasBytes);
 
     Frags<Pol, IN, kLds> fr{frag_lds, params, out, po};
-    if constexpr (kLds) fill_all_tables<Pol, IN>(frag_lds, params, out, po);
+    if constexpr (kLds) fill_all_tables<Pol, IN, NW>(frag_lds, params, out, po);
     for (int t = threadIdx.x; t < 128; t += blockDim.x)
         bias_lds[t] = (V)Pol::bias(params[t < 64 ? po.b1 + t : po.b2 + t - 64]);
     __syncthreads();
@@ -962,9 +966,10 @@ constexpr int kMlpFwdMaxBlocks = 1024;
 constexpr int kMlpBwdMaxBlocks = 256;
 constexpr int kMlpF64MaxBlocks = 64;   // the FP64 check path spills to scratch: keep its grid small
 
-static int mlp_blocks(int n, int cap) {
+// One workgroup per `waves` tiles of 16 queries, at most `cap`.
+static int mlp_blocks(int n, int waves, int cap) {
     const int ntiles = (n + 15) / 16;
-    const int want = (ntiles + kWaves - 1) / kWaves;
+    const int want = (ntiles + waves - 1) / waves;
     return want < cap ? (want > 0 ? want : 1) : cap;
 }
 
@@ -986,7 +991,7 @@ static hipError_t forward_t(const MlpBatch& b, int blocks, int out, hipStream_t 
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kMlpBlock), lds, s, b, out);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(fwd_threads<Pol, IN>()), lds, s, b, out);
     return hipGetLastError();
 }
 
@@ -1044,7 +1049,7 @@ static int log2i(int F) { return F == 1 ? 0 : F == 2 ? 1 : F == 4 ? 2 : 3; }
 
 int mlp_blocks_for(h4d_dtype dt, bool backward, int64_t queries) {
     const int cap = dt == H4D_F64 ? kMlpF64MaxBlocks : backward ? kMlpBwdMaxBlocks : kMlpFwdMaxBlocks;
-    return mlp_blocks((int)(queries < 2147483647 ? queries : 2147483647), cap);
+    return mlp_blocks((int)(queries < 2147483647 ? queries : 2147483647), backward ? 8 : 4, cap);
 }
 
 size_t mlp_partial_bytes(h4d_dtype dt, int in, int out, int blocks, int) {
