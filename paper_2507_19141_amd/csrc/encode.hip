@@ -112,7 +112,8 @@ __device__ __forceinline__ uint32_t query_tile_mask(const DevGrid& g, const Tile
 
 // Grid (ceil(n / kEncodeBlock), L).  Hashed levels: one query per thread.  Dense
 // levels: the first ceil(n / kMaskChunk) workgroups take kMaskChunk queries each and
-// also count, per tile bit, the queries that touch it (counts[l][chunk][32]).
+// also count, per tile bit, the queries that touch it (counts[l][32][chunk]: bit-major,
+// so that the plan sums a bit's chunks with contiguous loads).
 template <bool PAIR>
 __global__ __launch_bounds__(kEncodeBlock) void k_tile_mask(DevGrid g, TileMap tm, const float4* __restrict__ xyzt,
                                                             const float4* __restrict__ eps, int n,
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kEncodeBlock) void k_tile_mask(DevGrid g, TileMap t
         }
     }
     __syncthreads();
-    if (threadIdx.x < 32) counts[((int64_t)l * nchunks + chunk) * 32 + threadIdx.x] = cnt[threadIdx.x];
+    if (threadIdx.x < 32) counts[((int64_t)l * 32 + threadIdx.x) * nchunks + chunk] = cnt[threadIdx.x];
 }
 
 // The plan.  Entry t < tiles is tile t's first (or only) query range; entries tiles
@@ -178,7 +179,10 @@ __global__ __launch_bounds__(1024) void k_tile_plan(DevGrid g, TileMap tm, const
     // queries per dense tile from the (tile bit, chunk) counts of the dense levels.
     // Item i = (the (i / 32)-th dense level, bit i % 32); wavefront w sums items w,
     // w + nwaves, ... four at a time, each lane loading chunks lane, lane + 64, ... of
-    // all four before adding any, then a butterfly; so no two lanes add into one word.
+    // all four before adding any (contiguous in the bit-major counts: 256 bytes per
+    // load instruction; with chunk-major counts every lane's load was a line of its
+    // own and this phase took 21 k cycles instead of 13 k), then a butterfly; so no
+    // two lanes add into one word.
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
     const float whole = target0 * (2.f / 1.25f);
     if (threadIdx.x == 0) target_s = target0;
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(1024) void k_tile_plan(DevGrid g, TileMap tm, const
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int k = k0 + c * 64 + lane;
-                    v[j][c] = ok[j] && k < nchunks ? counts[((int64_t)lv[j] * nchunks + k) * 32 + bit[j]] : 0u;
+                    v[j][c] = ok[j] && k < nchunks ? counts[((int64_t)lv[j] * 32 + bit[j]) * nchunks + k] : 0u;
                 }
 #pragma unroll
             for (int j = 0; j < 4; ++j) sum[j] += (v[j][0] + v[j][1]) + (v[j][2] + v[j][3]);
@@ -641,7 +645,7 @@ TileMap make_tile_map(const DevGrid& g, const int64_t* level_rows, int F, int gb
 }
 
 // Workspace of the tiled scatter, each part 256-byte aligned: masks [L][stride] u32 |
-// pair tile bytes [L][stride] uint2 | per-chunk tile counts [L][chunks][32] u32 | plan
+// pair tile bytes [L][stride] uint2 | per-chunk tile counts [L][32][chunks] u32 | plan
 // [tiles + extra] int4 | plan info (2 int) | split tiles [extra] int | partial tiles
 // [2 extra][slot].  One layout serves FP32 and FP64 gradients (the larger tile count
 // and tile of the two).

@@ -502,12 +502,11 @@ struct Stage<PolF32> {
 
 template <>
 struct Stage<PolBF16> {
-    using T = uint16_t;  // BF16 bit patterns, rounded to nearest even once when staged
+    using T = uint16_t;  // BF16 bit patterns, rounded to nearest even once (put_tile)
     static constexpr int QG = 32, PAD = 8;
     struct Grp {
         bf16x8 v;
     };
-    __device__ static void put(T* p, float v) { *p = __builtin_bit_cast(uint16_t, (__bf16)v); }
     __device__ static Grp load(const T* row, int m) {
         return Grp{__builtin_bit_cast(
             bf16x8, *reinterpret_cast<const ushortx8*>(row + QG * m + 8 * ((threadIdx.x & 63) >> 4)))};
