@@ -284,6 +284,35 @@ def test_deform_path_paper_scene_full_size(shared):
     scaled_close(d_table, O.encode_backward(x, rf, og), O.encode_backward(x, sf, og), RTOL_GRAD, "d_table 200k")
 
 
+def test_deform_path_paper_scene_full_size_bf16():
+    # The BF16 form at the benchmark's configuration (n = 200k clustered, L = 16,
+    # T = 2^19): BF16 tables and decoder cast on the GPU from FP32 masters, upstream
+    # gradient loss-scaled by 4096; delta on 4096 sampled queries, d_params and the whole
+    # d_table element by element against the oracle's chain on the FP32 masters.
+    import torch
+    w = synth.PAPER_SCENE
+    og, lg = oracle_grid(w), lib_grid(w)
+    rng, x = synth.scene_inputs(w.n, 105)
+    table = synth.table_init(og.E, w.F, rng)
+    params = synth.decoder_params(w.n_in, rng)
+    gd = synth.upstream(w.n, 10, rng)
+    tb = torch.empty(table.size, dtype=torch.int16, device="cuda")
+    pb = torch.empty(params.size, dtype=torch.int16, device="cuda")
+    _lib.h4d_cast_bf16(dev(table), tb, table.size)
+    _lib.h4d_cast_bf16(dev(params), pb, params.size)
+    feat, delta, d_table, d_params = run_deform(lg, _lib.BF16, tb, pb, x, gd, w.n_in, og.E, w.F,
+                                                loss_scale=4096.0, grad_scale=1 / 4096.0)
+    idx = np.random.default_rng(106).choice(w.n, 4096, replace=False)
+    _, d_ref = O.deform_forward(x[idx], table, og, params)
+    f_scale_s = O.encode(x[idx], np.abs(table), og)
+    scaled_close(delta[idx], d_ref, mlp_forward_scale(params, f_scale_s), RTOL_BF16, "bf16 delta 200k")
+    f_ref = O.encode(x, table, og)
+    rf, rp = O.mlp_backward(params, f_ref, gd)
+    sf, sp = mlp_backward_scale(params, f_ref, gd)
+    scaled_close(d_params, rp, sp, RTOL_BF16, "bf16 d_params 200k")
+    scaled_close(d_table, O.encode_backward(x, rf, og), O.encode_backward(x, sf, og), RTOL_BF16, "bf16 d_table 200k")
+
+
 def test_deform_apply_eq10_bit_exact():
     import torch
     rng = np.random.default_rng(110)
