@@ -51,6 +51,9 @@ def parse():
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE passes); prints the step kernels' names")
     ap.add_argument("--counters-form", default="fp32", choices=("fp32", "bf16"),
                     help="the form the --counters run steps")
+    ap.add_argument("--fetch-calibration", action="store_true",
+                    help="only 2^22 random 8-byte loads over a 2 GiB table (twice) and one 256 MiB copy: the "
+                         "kernels that check the FETCH_SIZE scaling on random and streaming reads")
     ap.add_argument("--probe-sweep", action="store_true",
                     help="only run the gather / atomic probes over several footprints and print them")
     ap.add_argument("--cpu-sample", type=int, default=200000, help="queries the CPU oracle is timed on")
@@ -715,6 +718,18 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"counters_run": {"form": args.counters_form, "steps": args.steps + 1, "copy_bytes": nbytes,
                                            "copy_kernel": "k_probe_copy"}}), flush=True)
+        return
+    if args.fetch_calibration:
+        big = torch.zeros(2 << 30, dtype=torch.uint8, device="cuda")
+        sink = torch.zeros(1 << 20, device="cuda")
+        for seed in (1, 2):
+            _lib.h4d_probe_gather(big, (2 << 30) // 8, 8, 1 << 22, seed, sink)
+        src = torch.ones(1 << 26, device="cuda")
+        dst = torch.empty_like(src)
+        _lib.h4d_probe_copy(src, dst, 1 << 28)
+        torch.cuda.synchronize()
+        print(json.dumps({"fetch_calibration": {"gather_loads": 1 << 22, "gather_table_bytes": 2 << 30,
+                                                "copy_bytes": 1 << 28}}), flush=True)
         return
     if args.probe_sweep:
         w = synth.PAPER_SCENE
