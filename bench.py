@@ -32,7 +32,8 @@ KERNEL_SOURCES = ("encode.hip", "h4d_device.h", "h4d_internal.h", "mlp.hip")
 # the library kernels behind each timed part of the step
 STEP_KERNELS = {"cast": ["k_cast_bf16"], "encode": ["k_encode"], "decode": ["k_mlp_forward"],
                 "decode_bwd": ["k_mlp_backward", "k_mlp_reduce"],
-                "scatter": ["k_tile_mask", "k_tile_plan", "k_scatter_tiled", "k_tile_combine"]}
+                "scatter": ["k_tile_mask", "k_tile_plan", "k_scatter_tiled", "k_tile_combine"],
+                "check": ["k_count_nonfinite"]}
 TRAFFIC_FILE = os.path.join("profiles", "traffic_deform_paper_scene_fp32.md")
 
 
@@ -105,7 +106,8 @@ class Path:
             self.params_lo = torch.empty(params.size, dtype=torch.int16, device="cuda")
             self.counter = torch.zeros(1, dtype=torch.int32, device="cuda")
             self.loss_scale = 4096.0
-        self.names = (["cast"] if form == "bf16" else []) + ["encode", "decode", "decode_bwd", "scatter"]
+        self.names = (["cast"] if form == "bf16" else []) + ["encode", "decode", "decode_bwd", "scatter"] + \
+            (["check"] if form == "bf16" else [])
 
     def step(self, ev=None):
         L_, t = self.L_, self.torch
@@ -137,11 +139,16 @@ class Path:
         L_.deform_mlp_backward(self.m, self.dt, params, self.feat, self.n, self.d_delta, S, 1.0 / S, self.d_feat,
                                self.d_params, self.ws, self.ws_bytes, LM | L_.GRAD_OVERWRITE, F)
         mark()
-        L_.hash4d_encode_backward(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0, self.d_table, self.sws,
-                                  self.sws_bytes, LM | L_.GRAD_OVERWRITE)
         if self.form == "bf16":
-            L_.h4d_count_nonfinite(self.d_table, self.E * F, self.counter)
+            # the overflow test: the scatter counts the non-finite values it writes (all of
+            # d_table); the decoder gradient is counted by a pass of its own
+            L_.hash4d_encode_backward_checked(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0, self.d_table,
+                                              self.sws, self.sws_bytes, self.counter, LM | L_.GRAD_OVERWRITE)
+            mark()
             L_.h4d_count_nonfinite(self.d_params, self.d_params.numel(), self.counter)
+        else:
+            L_.hash4d_encode_backward(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0, self.d_table, self.sws,
+                                      self.sws_bytes, LM | L_.GRAD_OVERWRITE)
         mark()
 
     def step_smooth(self, eps, loss, sws, swb, lam: float, merged: bool):

@@ -182,6 +182,15 @@ size_t hash4d_encode_backward_workspace_bytes(const h4d_grid* g, int64_t n);
 h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
                                   h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
                                   void* workspace, size_t ws_bytes, void* stream);
+/* hash4d_encode_backward that also checks its output for the loss-scaled (BF16) form
+ * (the overflow test of mixed-precision training: a non-finite gradient skips the
+ * step and lowers the loss scale): *nonfinite (device int32) += the number of NaN or
+ * infinite values among the d_table values the call writes; with H4D_GRAD_OVERWRITE
+ * that is every value of d_table, so the count replaces a separate pass over it.
+ * Otherwise as hash4d_encode_backward.  nonfinite: non-NULL, 4-byte aligned. */
+h4d_status hash4d_encode_backward_checked(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
+                                          h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
+                                          void* workspace, size_t ws_bytes, int32_t* nonfinite, void* stream);
 
 /* hash4d_encode_backward without a workspace argument and without any device
  * allocation, for callers that cannot allocate: code under HIP graph capture, tight

@@ -117,6 +117,7 @@ SIGNATURES = {
     "hash4d_encode": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _P]),
     "hash4d_encode_backward_workspace_bytes": (_SZ, [_GP, _I64]),
     "hash4d_encode_backward": (_I32, [_GP, _I32, _P, _I64, _I32, _P, _F32, _P, _P, _SZ, _P]),
+    "hash4d_encode_backward_checked": (_I32, [_GP, _I32, _P, _I64, _I32, _P, _F32, _P, _P, _SZ, _P, _P]),
     "hash4d_encode_backward_noalloc": (_I32, [_GP, _I32, _P, _I64, _I32, _P, _F32, _P, _P]),
     "hash4d_encode_backward_input_workspace_bytes": (_SZ, [_GP, _I32, _I64]),
     "hash4d_encode_backward_input": (_I32, [_GP, _I32, _P, _P, _I64, _I32, _P, _F32, _P, _P, _SZ, _P]),
@@ -251,6 +252,15 @@ def hash4d_encode_backward(g: Grid, grad_dt: int, xyzt, n: int, d_feat, grad_sca
     _check("hash4d_encode_backward",
            load().hash4d_encode_backward(ctypes.byref(g), grad_dt, ptr(xyzt), n, layout, ptr(d_feat), grad_scale,
                                          ptr(d_table), ptr(workspace), ws_bytes, stream_handle(stream)))
+
+
+def hash4d_encode_backward_checked(g: Grid, grad_dt: int, xyzt, n: int, d_feat, grad_scale: float, d_table,
+                                   workspace, ws_bytes: int, nonfinite, layout: int = QUERY_MAJOR,
+                                   stream=None) -> None:
+    _check("hash4d_encode_backward_checked",
+           load().hash4d_encode_backward_checked(ctypes.byref(g), grad_dt, ptr(xyzt), n, layout, ptr(d_feat),
+                                                 grad_scale, ptr(d_table), ptr(workspace), ws_bytes, ptr(nonfinite),
+                                                 stream_handle(stream)))
 
 
 def hash4d_encode_backward_noalloc(g: Grid, grad_dt: int, xyzt, n: int, d_feat, grad_scale: float, d_table,

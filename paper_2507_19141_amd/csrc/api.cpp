@@ -357,7 +357,7 @@ size_t hash4d_encode_backward_workspace_bytes(const h4d_grid* g, int64_t n) {
 static h4d_status encode_backward_call(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
                                        h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
                                        void* workspace, size_t ws_bytes, bool static_ws, void* stream,
-                                       const char* where) {
+                                       const char* where, int32_t* nonfinite = nullptr) {
     g_last_error.clear();
     h4d_status st;
     int64_t ls, qs;
@@ -388,7 +388,8 @@ static h4d_status encode_backward_call(const h4d_grid* g, h4d_dtype grad_dt, con
     int64_t rows[H4D_MAX_LEVELS];
     rows_of(*g, rows);
     return hip_status(launch_scatter_tiled(d, rows, grad_dt, xyzt, nullptr, (int)n, d_feat, ls, qs,
-                                           (double)grad_scale, d_table, workspace, (hipStream_t)stream, overwrite),
+                                           (double)grad_scale, d_table, workspace, (hipStream_t)stream, overwrite,
+                                           MainGradArg{}, nonfinite),
                       where);
 }
 
@@ -397,6 +398,15 @@ h4d_status hash4d_encode_backward(const h4d_grid* g, h4d_dtype grad_dt, const fl
                                   void* workspace, size_t ws_bytes, void* stream) {
     return encode_backward_call(g, grad_dt, xyzt, n, layout, d_feat, grad_scale, d_table, workspace, ws_bytes,
                                 false, stream, "hash4d_encode_backward");
+}
+
+h4d_status hash4d_encode_backward_checked(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,
+                                          h4d_layout layout, const void* d_feat, float grad_scale, void* d_table,
+                                          void* workspace, size_t ws_bytes, int32_t* nonfinite, void* stream) {
+    g_last_error.clear();
+    if (!nonfinite || (((uintptr_t)nonfinite) & 3u)) return fail(H4D_EINVAL, "nonfinite is NULL or not 4-byte aligned");
+    return encode_backward_call(g, grad_dt, xyzt, n, layout, d_feat, grad_scale, d_table, workspace, ws_bytes,
+                                false, stream, "hash4d_encode_backward_checked", nonfinite);
 }
 
 h4d_status hash4d_encode_backward_noalloc(const h4d_grid* g, h4d_dtype grad_dt, const float* xyzt, int64_t n,

@@ -461,6 +461,14 @@ __device__ __forceinline__ void scatter_pair_words(const DevGrid& g, const TileM
     drain(0);
 }
 
+// *counter += the non-finite values the wavefront's lanes counted (one atomic per
+// wavefront that has any).  Called by every lane of the wavefront.
+__device__ __forceinline__ void add_count(int* counter, int bad) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) bad += __shfl_xor(bad, d, 64);
+    if ((threadIdx.x & 63) == 0 && bad) atomicAdd(counter, bad);
+}
+
 template <typename G, int F, bool PAIR>
 __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, TileMap tm, const float4* __restrict__ xyzt,
                                                                 const float4* __restrict__ eps, int n,
@@ -471,7 +479,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
                                                                 G* __restrict__ partials, int slot_elems,
                                                                 const G* __restrict__ src, int64_t lstride,
                                                                 int64_t qstride, G scale, G* __restrict__ d_table,
-                                                                int overwrite, MainGrad<G> mg) {
+                                                                int overwrite, MainGrad<G> mg,
+                                                                int* __restrict__ nonfinite) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int queue[kQueueCap];
     __shared__ int2 overflow[PAIR ? 1 : kScatterBlock / 64 * kOverflowCap];
@@ -524,16 +533,27 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_tiled(DevGrid g, Tile
         return;
     }
     // the tile's rows have no other owner: add them to d_table, or with overwrite set
-    // write every row (the tiles of the levels cover all E rows)
+    // write every row (the tiles of the levels cover all E rows); count the non-finite
+    // values written if asked
     G* out = d_table + (size_t)base * F;
+    int bad = 0;
     if (overwrite) {
-        for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) out[i] = tile[i];
+        for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) {
+            const G v = tile[i];
+            out[i] = v;
+            bad += !__builtin_isfinite(v);
+        }
     } else {
         for (uint32_t i = threadIdx.x; i < cnt * F; i += kScatterBlock) {
             const G v = tile[i];
-            if (v != G(0)) out[i] += v;
+            if (v != G(0)) {
+                const G r = out[i] + v;
+                out[i] = r;
+                bad += !__builtin_isfinite(r);
+            }
         }
     }
+    if (nonfinite) add_count(nonfinite, bad);
 }
 
 // Rows of the split tiles: the sum of their ranges' partial tiles, in range order.
@@ -544,7 +564,8 @@ __global__ __launch_bounds__(256) void k_tile_combine(DevGrid g, TileMap tm, con
                                                       const int* __restrict__ plan_info,
                                                       const int* __restrict__ split,
                                                       const G* __restrict__ partials, int slot_elems,
-                                                      G* __restrict__ d_table, int overwrite) {
+                                                      G* __restrict__ d_table, int overwrite,
+                                                      int* __restrict__ nonfinite) {
     if ((int)blockIdx.x >= plan_info[1]) return;
     const int tix = split[blockIdx.x];
     const int4 pe = plan[tix];
@@ -555,12 +576,20 @@ __global__ __launch_bounds__(256) void k_tile_combine(DevGrid g, TileMap tm, con
     const uint32_t chunk = (values + kCombineParts - 1) / kCombineParts;
     const uint32_t lo = blockIdx.y * chunk, hi = min(values, lo + chunk);
     G* out = d_table + (size_t)(g.off[l] + first) * g.F;
+    int bad = 0;
     for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
         G v = partials[(int64_t)pe.w * slot_elems + i];
         for (int r = 1; r < pe.z; ++r) v += partials[(int64_t)(pe.w + r) * slot_elems + i];
-        if (overwrite) out[i] = v;
-        else if (v != G(0)) out[i] += v;
+        if (overwrite) {
+            out[i] = v;
+            bad += !__builtin_isfinite(v);
+        } else if (v != G(0)) {
+            const G s = out[i] + v;
+            out[i] = s;
+            bad += !__builtin_isfinite(s);
+        }
     }
+    if (nonfinite) add_count(nonfinite, bad);
 }
 
 __global__ __launch_bounds__(kEncodeBlock) void k_corner_indices(DevGrid g, const float4* __restrict__ xyzt, int n,
@@ -700,7 +729,7 @@ struct ScatterBufs {
 template <typename G, int F, bool PAIR>
 static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt, const float* eps, int n,
                           const ScatterBufs& b, const void* src, int64_t ls, int64_t qs, double scale, void* d_table,
-                          bool overwrite, const MainGradArg& main, hipStream_t s) {
+                          bool overwrite, const MainGradArg& main, int32_t* nonfinite, hipStream_t s) {
     auto kern = k_scatter_tiled<G, F, PAIR>;
     const size_t lds = (size_t)tm.max_rows * F * sizeof(G);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -711,18 +740,19 @@ static hipError_t tiled_f(const DevGrid& g, const TileMap& tm, const float* xyzt
                        b.words, b.plan, b.info, static_cast<G*>(b.partials),
                        (int)(b.slot_bytes / sizeof(G)), static_cast<const G*>(src), ls, qs, (G)scale,
                        static_cast<G*>(d_table), overwrite ? 1 : 0,
-                       MainGrad<G>{static_cast<const G*>(main.src), main.lstride, main.qstride, (G)main.scale});
+                       MainGrad<G>{static_cast<const G*>(main.src), main.lstride, main.qstride, (G)main.scale},
+                       nonfinite);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_combine<G>, dim3((unsigned)b.extra, kCombineParts), dim3(256), 0, s, g, tm, b.plan,
                        b.info, b.split, static_cast<const G*>(b.partials),
-                       (int)(b.slot_bytes / sizeof(G)), static_cast<G*>(d_table), overwrite ? 1 : 0);
+                       (int)(b.slot_bytes / sizeof(G)), static_cast<G*>(d_table), overwrite ? 1 : 0, nonfinite);
     return hipGetLastError();
 }
 
 template <typename G, bool PAIR>
 static hipError_t tiled_g(const DevGrid& g, const int64_t* level_rows, const float* xyzt, const float* eps, int n,
                           const void* src, int64_t ls, int64_t qs, double scale, void* d_table, void* mask_ws,
-                          bool overwrite, const MainGradArg& main, hipStream_t s) {
+                          bool overwrite, const MainGradArg& main, int32_t* nonfinite, hipStream_t s) {
     const TileMap tm = make_tile_map(g, level_rows, g.F, (int)sizeof(G), !PAIR);
     const ScatterWs w = scatter_ws(g, level_rows, n);
     char* ws = static_cast<char*>(mask_ws);
@@ -752,10 +782,10 @@ static hipError_t tiled_g(const DevGrid& g, const int64_t* level_rows, const flo
                        (float)std::max(1.25 * h, 1024.0), w.extra, b.plan, b.info, b.split);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     switch (g.F) {
-        case 1: return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, s);
-        case 2: return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, s);
-        case 4: return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, s);
-        case 8: return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, s);
+        case 1: return tiled_f<G, 1, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, nonfinite, s);
+        case 2: return tiled_f<G, 2, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, nonfinite, s);
+        case 4: return tiled_f<G, 4, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, nonfinite, s);
+        case 8: return tiled_f<G, 8, PAIR>(g, tm, xyzt, eps, n, b, src, ls, qs, scale, d_table, overwrite, main, nonfinite, s);
     }
     return hipErrorInvalidValue;
 }
@@ -763,18 +793,18 @@ static hipError_t tiled_g(const DevGrid& g, const int64_t* level_rows, const flo
 hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d_dtype grad_dt, const float* xyzt,
                                 const float* eps, int n, const void* src, int64_t ls, int64_t qs, double scale,
                                 void* d_table, void* mask_ws, hipStream_t s, bool overwrite,
-                                const MainGradArg& main) {
+                                const MainGradArg& main, int32_t* nonfinite) {
     if (main.src && !eps) return hipErrorInvalidValue;  // the second gradient rides on the pair form only
     if (grad_dt == H4D_F64) {
         return eps ? tiled_g<double, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws,
-                                           overwrite, main, s)
+                                           overwrite, main, nonfinite, s)
                    : tiled_g<double, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws,
-                                            overwrite, main, s);
+                                            overwrite, main, nonfinite, s);
     }
     return eps ? tiled_g<float, true>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, overwrite,
-                                      main, s)
+                                      main, nonfinite, s)
                : tiled_g<float, false>(g, level_rows, xyzt, eps, n, src, ls, qs, scale, d_table, mask_ws, overwrite,
-                                       main, s);
+                                       main, nonfinite, s);
 }
 
 // ------------------------------------------ static workspace (no allocation) ----

@@ -95,7 +95,7 @@ struct MainGradArg {
 hipError_t launch_scatter_tiled(const DevGrid& g, const int64_t* level_rows, h4d_dtype grad_dt, const float* xyzt,
                                 const float* eps, int n, const void* src, int64_t lstride, int64_t qstride,
                                 double scale, void* d_table, void* mask_ws, hipStream_t s, bool overwrite = false,
-                                const MainGradArg& main = MainGradArg{});
+                                const MainGradArg& main = MainGradArg{}, int32_t* nonfinite = nullptr);
 // The static workspace of hash4d_encode_backward_noalloc: kStaticScratchBytes of
 // device memory per GPU (a file-scope array), its address on the current device.
 constexpr size_t kStaticScratchBytes = (size_t)64 << 20;

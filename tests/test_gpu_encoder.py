@@ -281,6 +281,52 @@ def test_encode_backward_overwrite(dt):
     assert (host(d) == 0).all()
 
 
+@pytest.mark.parametrize("case", ["small", "paper-shared-frame-150"])
+def test_encode_backward_checked_counts_nonfinite(case):
+    # hash4d_encode_backward_checked adds the NaN / infinite values among the table
+    # values it writes to its counter: with d_table finite beforehand, exactly the
+    # non-finite values of the result, in both write modes.  The paper scene with
+    # every query at frame 150 splits heavy dense tiles, so the combine kernel's
+    # writes are counted too; inf and NaN are planted in level 0's (dense) gradient.
+    import torch
+    if case == "small":
+        og, lg, x, _, rng = encoder_case(synth.ENCODER_SMALL, 1500, 13)
+    else:
+        w = synth.PAPER_SCENE
+        og, lg = oracle_grid(w), lib_grid(w)
+        rng, x = synth.scene_inputs(w.n, 107, shared_frame=150)
+    n = x.shape[0]
+    gf = synth.upstream(n, og.L * og.F, rng).reshape(n, og.L, og.F).transpose(1, 0, 2).copy()  # [L, n, F]
+    wb = _lib.hash4d_encode_backward_workspace_bytes(lg, n)
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    counter = torch.zeros(1, dtype=torch.int32, device="cuda")
+    d = torch.zeros((og.E, og.F), device="cuda")
+    # finite gradients: nothing counted, same values as the unchecked call
+    _lib.hash4d_encode_backward_checked(lg, _lib.F32, dev(x), n, dev(gf), 0.5, d, ws, wb, counter,
+                                        _lib.LEVEL_MAJOR | _lib.GRAD_OVERWRITE)
+    ref = torch.zeros_like(d)
+    _lib.hash4d_encode_backward(lg, _lib.F32, dev(x), n, dev(gf), 0.5, ref, ws, wb,
+                                _lib.LEVEL_MAJOR | _lib.GRAD_OVERWRITE)
+    assert int(host(counter)[0]) == 0
+    scale = O.encode_backward(x, np.abs(gf.transpose(1, 0, 2).reshape(n, -1)), og, 0.5)
+    scaled_close(host(d), host(ref), scale, RTOL_GRAD, "checked = unchecked")
+    bad = gf.copy()
+    bad[0, 0:7, 0] = np.inf
+    bad[0, 7:11, 1] = -np.inf
+    bad[0, 11:13, 0] = np.nan
+    for mode in (_lib.GRAD_OVERWRITE, 0):
+        counter.zero_()
+        d.zero_()
+        _lib.hash4d_encode_backward_checked(lg, _lib.F32, dev(x), n, dev(bad), 0.5, d, ws, wb, counter,
+                                            _lib.LEVEL_MAJOR | mode)
+        want = int((~torch.isfinite(d)).sum())
+        assert want > 0
+        assert int(host(counter)[0]) == want, (mode, int(host(counter)[0]), want)
+    with pytest.raises(RuntimeError):
+        _lib.hash4d_encode_backward_checked(lg, _lib.F32, dev(x), n, dev(gf), 0.5, d, ws, wb, None,
+                                            _lib.LEVEL_MAJOR)
+
+
 # The configuration the benchmark times (n = 200k clustered queries, L = 16, T = 2^19),
 # with each query at its own frame and with every query at frame 150 of 300 (one
 # view per training iteration): the whole table gradient, row by row, against the
