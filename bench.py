@@ -32,8 +32,7 @@ KERNEL_SOURCES = ("encode.hip", "h4d_device.h", "h4d_internal.h", "mlp.hip")
 # the library kernels behind each timed part of the step
 STEP_KERNELS = {"cast": ["k_cast_bf16"], "encode": ["k_encode"], "decode": ["k_mlp_forward"],
                 "decode_bwd": ["k_mlp_backward", "k_mlp_reduce"],
-                "scatter": ["k_tile_mask", "k_tile_plan", "k_scatter_tiled", "k_tile_combine"],
-                "check": ["k_count_nonfinite"]}
+                "scatter": ["k_tile_mask", "k_tile_plan", "k_scatter_tiled", "k_tile_combine"]}
 TRAFFIC_FILE = os.path.join("profiles", "traffic_deform_paper_scene_fp32.md")
 
 
@@ -106,8 +105,7 @@ class Path:
             self.params_lo = torch.empty(params.size, dtype=torch.int16, device="cuda")
             self.counter = torch.zeros(1, dtype=torch.int32, device="cuda")
             self.loss_scale = 4096.0
-        self.names = (["cast"] if form == "bf16" else []) + ["encode", "decode", "decode_bwd", "scatter"] + \
-            (["check"] if form == "bf16" else [])
+        self.names = (["cast"] if form == "bf16" else []) + ["encode", "decode", "decode_bwd", "scatter"]
 
     def step(self, ev=None):
         L_, t = self.L_, self.torch
@@ -136,16 +134,19 @@ class Path:
         mark()
         # the decoder backward scales d_delta by S on load and writes d_feat and
         # d_params times 1 / S, so the scatter takes d_feat unscaled (grad_scale 1)
-        L_.deform_mlp_backward(self.m, self.dt, params, self.feat, self.n, self.d_delta, S, 1.0 / S, self.d_feat,
-                               self.d_params, self.ws, self.ws_bytes, LM | L_.GRAD_OVERWRITE, F)
+        if self.form == "bf16":
+            # the overflow test: both backward calls count the non-finite values they
+            # write (all of d_params and d_table)
+            L_.deform_mlp_backward_checked(self.m, self.dt, params, self.feat, self.n, self.d_delta, S, 1.0 / S,
+                                           self.d_feat, self.d_params, self.ws, self.ws_bytes, self.counter,
+                                           LM | L_.GRAD_OVERWRITE, F)
+        else:
+            L_.deform_mlp_backward(self.m, self.dt, params, self.feat, self.n, self.d_delta, S, 1.0 / S, self.d_feat,
+                                   self.d_params, self.ws, self.ws_bytes, LM | L_.GRAD_OVERWRITE, F)
         mark()
         if self.form == "bf16":
-            # the overflow test: the scatter counts the non-finite values it writes (all of
-            # d_table); the decoder gradient is counted by a pass of its own
             L_.hash4d_encode_backward_checked(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0, self.d_table,
                                               self.sws, self.sws_bytes, self.counter, LM | L_.GRAD_OVERWRITE)
-            mark()
-            L_.h4d_count_nonfinite(self.d_params, self.d_params.numel(), self.counter)
         else:
             L_.hash4d_encode_backward(self.g, L_.F32, self.xyzt, self.n, self.d_feat, 1.0, self.d_table, self.sws,
                                       self.sws_bytes, LM | L_.GRAD_OVERWRITE)

@@ -380,6 +380,15 @@ h4d_status deform_mlp_forward(const h4d_mlp* m, h4d_dtype dt, const void* params
 h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* params, const void* feat, int64_t n,
                                h4d_layout layout, int32_t F, const void* d_out, float loss_scale, float grad_scale,
                                void* d_feat, void* d_params, void* workspace, size_t ws_bytes, void* stream);
+/* deform_mlp_backward that also checks its parameter gradient for the loss-scaled
+ * (BF16) form's overflow test: *nonfinite (device int32) += the number of NaN or
+ * infinite values among the d_params values it writes (all of them with
+ * H4D_GRAD_OVERWRITE; n = 0 writes zeros and counts nothing).  Otherwise as
+ * deform_mlp_backward.  nonfinite: non-NULL, 4-byte aligned. */
+h4d_status deform_mlp_backward_checked(const h4d_mlp* m, h4d_dtype dt, const void* params, const void* feat,
+                                       int64_t n, h4d_layout layout, int32_t F, const void* d_out, float loss_scale,
+                                       float grad_scale, void* d_feat, void* d_params, void* workspace,
+                                       size_t ws_bytes, int32_t* nonfinite, void* stream);
 
 /* -------------------------------------------------- deformation path ---- */
 

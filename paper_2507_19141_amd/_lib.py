@@ -132,6 +132,8 @@ SIGNATURES = {
     "deform_mlp_workspace_bytes": (_SZ, [_MP, _I32, _I64]),
     "deform_mlp_forward": (_I32, [_MP, _I32, _P, _P, _I64, _I32, _I32, _P, _P]),
     "deform_mlp_backward": (_I32, [_MP, _I32, _P, _P, _I64, _I32, _I32, _P, _F32, _F32, _P, _P, _P, _SZ, _P]),
+    "deform_mlp_backward_checked": (_I32, [_MP, _I32, _P, _P, _I64, _I32, _I32, _P, _F32, _F32, _P, _P, _P, _SZ, _P,
+                                           _P]),
     "hash4d_deform_workspace_bytes": (_SZ, [_GP, _MP, _I32, _I64]),
     "hash4d_deform_forward": (_I32, [_GP, _MP, _I32, _P, _P, _P, _I64, _P, _P, _P]),
     "hash4d_deform_backward": (_I32, [_GP, _MP, _I32, _P, _P, _I64, _P, _P, _F32, _F32, _P, _P, _P, _SZ, _P]),
@@ -345,6 +347,15 @@ def deform_mlp_backward(m: Mlp, dt: int, params, feat, n: int, d_out, loss_scale
            load().deform_mlp_backward(ctypes.byref(m), dt, ptr(params), ptr(feat), n, layout, F, ptr(d_out),
                                       loss_scale, grad_scale, ptr(d_feat), ptr(d_params), ptr(workspace), ws_bytes,
                                       stream_handle(stream)))
+
+
+def deform_mlp_backward_checked(m: Mlp, dt: int, params, feat, n: int, d_out, loss_scale: float, grad_scale: float,
+                                d_feat, d_params, workspace, ws_bytes: int, nonfinite, layout: int = QUERY_MAJOR,
+                                F: int = 0, stream=None) -> None:
+    _check("deform_mlp_backward_checked",
+           load().deform_mlp_backward_checked(ctypes.byref(m), dt, ptr(params), ptr(feat), n, layout, F, ptr(d_out),
+                                              loss_scale, grad_scale, ptr(d_feat), ptr(d_params), ptr(workspace),
+                                              ws_bytes, ptr(nonfinite), stream_handle(stream)))
 
 
 # ------------------------------------------------------ deformation path ----

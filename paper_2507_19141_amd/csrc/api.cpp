@@ -726,10 +726,10 @@ h4d_status deform_mlp_forward(const h4d_mlp* m, h4d_dtype dt, const void* params
                       "deform_mlp_forward");
 }
 
-h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* params, const void* feat, int64_t n,
-                               h4d_layout layout, int32_t F, const void* d_out, float loss_scale, float grad_scale,
-                               void* d_feat, void* d_params, void* workspace, size_t ws_bytes, void* stream) {
-    g_last_error.clear();
+static h4d_status mlp_backward_call(const h4d_mlp* m, h4d_dtype dt, const void* params, const void* feat,
+                                    int64_t n, h4d_layout layout, int32_t F, const void* d_out, float loss_scale,
+                                    float grad_scale, void* d_feat, void* d_params, void* workspace, size_t ws_bytes,
+                                    int32_t* nonfinite, void* stream) {
     h4d_status st;
     int Fk;
     int64_t ls, qs;
@@ -750,8 +750,26 @@ h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* param
     if (((uintptr_t)workspace) & 15u) return fail(H4D_EINVAL, "workspace is not 16-byte aligned");
     return hip_status(launch_mlp_backward(dt, m->in, m->out, params, feat, Fk, ls, qs, (int)n, d_out, loss_scale,
                                           grad_scale, grad_scale, d_feat, ls, qs, d_params, workspace,
-                                          (hipStream_t)stream, overwrite),
+                                          (hipStream_t)stream, overwrite, nonfinite),
                       "deform_mlp_backward");
+}
+
+h4d_status deform_mlp_backward(const h4d_mlp* m, h4d_dtype dt, const void* params, const void* feat, int64_t n,
+                               h4d_layout layout, int32_t F, const void* d_out, float loss_scale, float grad_scale,
+                               void* d_feat, void* d_params, void* workspace, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return mlp_backward_call(m, dt, params, feat, n, layout, F, d_out, loss_scale, grad_scale, d_feat, d_params,
+                             workspace, ws_bytes, nullptr, stream);
+}
+
+h4d_status deform_mlp_backward_checked(const h4d_mlp* m, h4d_dtype dt, const void* params, const void* feat,
+                                       int64_t n, h4d_layout layout, int32_t F, const void* d_out, float loss_scale,
+                                       float grad_scale, void* d_feat, void* d_params, void* workspace,
+                                       size_t ws_bytes, int32_t* nonfinite, void* stream) {
+    g_last_error.clear();
+    if (!nonfinite || (((uintptr_t)nonfinite) & 3u)) return fail(H4D_EINVAL, "nonfinite is NULL or not 4-byte aligned");
+    return mlp_backward_call(m, dt, params, feat, n, layout, F, d_out, loss_scale, grad_scale, d_feat, d_params,
+                             workspace, ws_bytes, nonfinite, stream);
 }
 
 h4d_status hash4d_deform_apply(const float* delta, int64_t n, int32_t out, const float* xyz, const float* rot,

@@ -155,6 +155,7 @@ struct MlpBatch {
     MlpSpan s[kMaxMlpSpans];
     int count;
     int overwrite;  // 1: d_params is written (=) instead of accumulated (+=)
+    int* nonfinite; // non-NULL: += the non-finite d_params values written
 };
 
 // Persistent-grid size of the decoder kernels for a total of `queries` queries.
@@ -174,7 +175,8 @@ hipError_t launch_mlp_forward(h4d_dtype dt, int in, int out, const void* params,
 hipError_t launch_mlp_backward(h4d_dtype dt, int in, int out, const void* params, const void* feat, int F,
                                int64_t lstride, int64_t qstride, int n, const void* d_out, double in_scale,
                                double feat_scale, double param_scale, void* d_feat, int64_t dlstride,
-                               int64_t dqstride, void* d_params, void* ws, hipStream_t s, bool overwrite = false);
+                               int64_t dqstride, void* d_params, void* ws, hipStream_t s, bool overwrite = false,
+                               int32_t* nonfinite = nullptr);
 
 // ---- precision helpers (precision.hip) ----
 hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s);

@@ -947,13 +947,20 @@ __global__ __launch_bounds__(kRedParams * kRedGroups) void k_mlp_reduce(MlpBatch
     }
     part[grp][pl] = s;
     __syncthreads();
+    int bad = 0;
     if (grp == 0 && p < P) {
         G t = G(0);
 #pragma unroll
         for (int g = 0; g < kRedGroups; ++g) t += part[g][pl];
         G* dp = static_cast<G*>(sp.d_params) + p;
-        if (batch.overwrite) *dp = scale * t;
-        else *dp += scale * t;
+        const G v = batch.overwrite ? scale * t : *dp + scale * t;
+        *dp = v;
+        bad = !__builtin_isfinite(v);
+    }
+    if (batch.nonfinite) {  // one atomic per wavefront that wrote a non-finite value
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) bad += __shfl_xor(bad, d, 64);
+        if ((threadIdx.x & 63) == 0 && bad) atomicAdd(batch.nonfinite, bad);
     }
 }
 
@@ -1089,11 +1096,12 @@ hipError_t launch_mlp_forward(h4d_dtype dt, int in, int out, const void* params,
 hipError_t launch_mlp_backward(h4d_dtype dt, int in, int out, const void* params, const void* feat, int F,
                                int64_t lstride, int64_t qstride, int n, const void* d_out, double in_scale,
                                double feat_scale, double param_scale, void* d_feat, int64_t dlstride, int64_t dqstride,
-                               void* d_params, void* ws, hipStream_t s, bool overwrite) {
+                               void* d_params, void* ws, hipStream_t s, bool overwrite, int32_t* nonfinite) {
     if (dlstride != lstride || dqstride != qstride) return hipErrorInvalidValue;  // d_feat shares feat's layout
     const int blocks = mlp_blocks_for(dt, true, n);
     MlpBatch b = single(params, feat, nullptr, d_out, d_feat, d_params, F, lstride, qstride, n, blocks);
     b.overwrite = overwrite ? 1 : 0;
+    b.nonfinite = nonfinite;
     return launch_mlp_backward_batch(dt, in, out, b, blocks, in_scale, feat_scale, param_scale, ws, s);
 }
 

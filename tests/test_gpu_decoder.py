@@ -141,6 +141,45 @@ def test_mlp_backward_overwrite(dt):
     assert (host(wr) == 0).all()
 
 
+@pytest.mark.parametrize("dt", [_lib.F32, _lib.BF16], ids=["f32", "bf16"])
+def test_mlp_backward_checked_counts_nonfinite(dt):
+    # deform_mlp_backward_checked adds the NaN / infinite values among the d_params
+    # values it writes to its counter; the gradients equal the unchecked call's.
+    import torch
+    n_in, n = 32, 3000
+    params, f, g = decoder_case(n_in, n, 96)
+    p_dev = bf16_dev(params) if dt == _lib.BF16 else dev(params)
+    m = _lib.mlp_shape(n_in)
+    wb = _lib.deform_mlp_workspace_bytes(m, dt, n)
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    P = O.param_count(n_in)
+    counter = torch.zeros(1, dtype=torch.int32, device="cuda")
+    outs = []
+    for checked in (False, True):
+        d_feat = torch.empty((n, n_in), device="cuda")
+        d_params = torch.full((P,), float("nan"), device="cuda")
+        args = (m, dt, p_dev, dev(f), n, dev(g), 1.0, 1.0, d_feat, d_params, ws, wb)
+        if checked:
+            _lib.deform_mlp_backward_checked(*args, counter, _lib.QUERY_MAJOR | _lib.GRAD_OVERWRITE)
+        else:
+            _lib.deform_mlp_backward(*args, _lib.QUERY_MAJOR | _lib.GRAD_OVERWRITE)
+        outs.append((host(d_feat), host(d_params)))
+    assert int(host(counter)[0]) == 0
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    bad = g.copy()
+    bad[5, 0] = np.inf
+    bad[17, 3] = np.nan
+    d_feat = torch.empty((n, n_in), device="cuda")
+    for mode in (_lib.GRAD_OVERWRITE, 0):
+        counter.zero_()
+        d_params = torch.zeros(P, device="cuda")
+        _lib.deform_mlp_backward_checked(m, dt, p_dev, dev(f), n, dev(bad), 1.0, 1.0, d_feat, d_params, ws, wb,
+                                         counter, _lib.QUERY_MAJOR | mode)
+        want = int((~torch.isfinite(d_params)).sum())
+        assert want > 0
+        assert int(host(counter)[0]) == want, (mode, int(host(counter)[0]), want)
+
+
 @pytest.mark.parametrize("n_in", [8, 32])
 def test_mlp_backward_bf16_and_f64(n_in):
     params, f, g = decoder_case(n_in, 2048 + 7, 90 + n_in)
