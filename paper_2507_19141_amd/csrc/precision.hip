@@ -6,17 +6,22 @@ namespace h4d {
 
 constexpr int kCastBlock = 256;
 
-// dst[i] = RNE BF16 of src[i]; four elements per thread (16-byte loads, 8-byte stores).
+// dst[i] = RNE BF16 of src[i]; eight elements per thread (two 16-byte loads, one
+// 16-byte store).
 __global__ __launch_bounds__(kCastBlock) void k_cast_bf16(const float* __restrict__ src, uint16_t* __restrict__ dst,
                                                           int64_t count) {
-    const int64_t i4 = ((int64_t)blockIdx.x * kCastBlock + threadIdx.x) * 4;
-    if (i4 + 3 < count && ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) == 0) {
-        const float4 v = *reinterpret_cast<const float4*>(src + i4);
-        ushort4 o;
-        o.x = f32_to_bf16(v.x); o.y = f32_to_bf16(v.y); o.z = f32_to_bf16(v.z); o.w = f32_to_bf16(v.w);
-        *reinterpret_cast<ushort4*>(dst + i4) = o;
+    const int64_t i8 = ((int64_t)blockIdx.x * kCastBlock + threadIdx.x) * 8;
+    if (i8 + 7 < count && ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) == 0) {
+        const float4 a = *reinterpret_cast<const float4*>(src + i8);
+        const float4 b = *reinterpret_cast<const float4*>(src + i8 + 4);
+        uint4 o;
+        o.x = f32_to_bf16(a.x) | ((uint32_t)f32_to_bf16(a.y) << 16);
+        o.y = f32_to_bf16(a.z) | ((uint32_t)f32_to_bf16(a.w) << 16);
+        o.z = f32_to_bf16(b.x) | ((uint32_t)f32_to_bf16(b.y) << 16);
+        o.w = f32_to_bf16(b.z) | ((uint32_t)f32_to_bf16(b.w) << 16);
+        *reinterpret_cast<uint4*>(dst + i8) = o;
     } else {
-        for (int64_t i = i4; i < count && i < i4 + 4; ++i) dst[i] = f32_to_bf16(src[i]);
+        for (int64_t i = i8; i < count && i < i8 + 8; ++i) dst[i] = f32_to_bf16(src[i]);
     }
 }
 
@@ -44,7 +49,7 @@ hipError_t launch_zero_words(void* p, int64_t words, hipStream_t s) {
 }
 
 hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s) {
-    const int64_t threads = (count + 3) / 4;
+    const int64_t threads = (count + 7) / 8;
     hipLaunchKernelGGL(k_cast_bf16, dim3((unsigned)((threads + kCastBlock - 1) / kCastBlock)), dim3(kCastBlock), 0, s,
                        src, dst, count);
     return hipGetLastError();
