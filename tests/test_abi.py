@@ -197,6 +197,21 @@ def test_entry_points_validate_without_launching():
     assert lib.deform_mlp_backward(mp, 0, fake, fake, 0, OW, 0, fake, 1.0, 1.0, fake, None, fake, 8, None) == -1
     assert lib.deform_mlp_backward(mp, 0, fake, fake, 0, 0, 0, fake, 1.0, 1.0, fake, None, fake, 8, None) == 0
     assert lib.deform_mlp_forward(mp, 0, fake, fake, 5, OW, 0, fake, None) == -1            # no gradient there
+    # the overflow-counting forms check their counter before anything else
+    ck = lib.deform_mlp_backward_checked
+    assert ck(mp, 0, fake, fake, 5, 0, 0, fake, 1.0, 1.0, fake, fake, fake, 1 << 20, None, None) == -1  # NULL
+    assert "nonfinite" in _lib.last_error()
+    assert ck(mp, 0, fake, fake, 5, 0, 0, fake, 1.0, 1.0, fake, fake, fake, 1 << 20, fake + 2, None) == -1
+    assert "aligned" in _lib.last_error()
+    eck = lib.hash4d_encode_backward_checked
+    assert eck(gp, 0, fake, 5, 0, fake, 1.0, fake, fake, 1 << 20, None, None) == -1              # NULL counter
+    assert "nonfinite" in _lib.last_error()
+    assert eck(gp, 0, fake, 5, 0, fake, 1.0, fake, fake, 1 << 20, fake + 1, None) == -1          # misaligned
+    assert eck(gp, 0, fake, 5, 0, fake, 1.0, fake, fake, 4, fake, None) == -1                   # then the rest
+    assert "workspace" in _lib.last_error()
+    assert lib.h4d_count_nonfinite(fake, -1, fake, None) == -1
+    assert lib.h4d_count_nonfinite(None, 0, None, None) == 0                                  # count 0: no-op
+    assert lib.h4d_count_nonfinite(None, 5, fake, None) == -1
 
 
 def test_query_count_limit_boundary():
